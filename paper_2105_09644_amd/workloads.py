@@ -1,0 +1,293 @@
+"""Seeded synthetic inputs for the TreeRay/OnTheSpot sweep.
+
+This module only *describes* problems: grids (uniform or block-structured
+adaptive), hydrogen number densities, point sources and run parameters.  It
+holds none of the method's arithmetic (no tree, no rays, no kernels), so both
+the HIP library and the FP64 CPU oracle can be fed from it.
+
+Grid description (shared by every consumer):
+
+* A domain is an array of ``nroot`` root blocks of 8^3 cells each, of side
+  ``root_block_cm``.  Blocks may be refined up to ``max_level`` times; a block
+  at level L has side ``root_block_cm / 2**L``.
+* ``leaf_blocks is None``: uniform grid (``max_level == 0``); cells are in
+  global C order over (x, y, z), z fastest -- the order of ``n_h.ravel()``
+  for an ``n_h[x, y, z]`` array.
+* otherwise ``leaf_blocks`` is an int32 array ``[n, 4] = (level, bi, bj, bk)``
+  with (bi, bj, bk) the block index at that level; cells are ordered block by
+  block, C order (x slowest, z fastest) inside each block.
+
+Physical setup (Sec. 3.1 of the paper for the constants): pure hydrogen,
+alpha_B = 2.7e-13 cm^3 s^-1 (Case B at 1e4 K), cubic boxes of side 4 pc with
+isolated boundaries.  Random streams use ``numpy.random.default_rng`` seeded
+with ``[2105, 9644, k]`` (config k) or ``[2105, 9644, 4, m]`` (domain m of
+the batched config).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+PC_CM = 3.0856775814913673e18
+ALPHA_B = 2.7e-13          # cm^3 s^-1, Case-B recombination coefficient at 1e4 K
+HNU_EUV_ERG = 13.6 * 1.602176634e-12   # mean EUV photon energy used to report e
+C_LIGHT = 2.99792458e10
+BOX_PC = 4.0
+BLOCK = 8
+
+
+@dataclass
+class Domain:
+    nroot: tuple                      # root blocks per axis
+    root_block_cm: float              # side of one root block
+    max_level: int = 0                # refinement levels above the root level
+    leaf_blocks: Optional[np.ndarray] = None   # int32 [n,4] (level, bi, bj, bk)
+
+    def n_cells(self) -> int:
+        if self.leaf_blocks is None:
+            return int(np.prod(self.nroot)) * BLOCK ** 3
+        return int(self.leaf_blocks.shape[0]) * BLOCK ** 3
+
+    def finest_dx_cm(self) -> float:
+        return self.root_block_cm / (BLOCK * 2 ** self.max_level)
+
+    def extent_finest(self) -> tuple:
+        f = BLOCK * 2 ** self.max_level
+        return tuple(int(n) * f for n in self.nroot)
+
+
+@dataclass
+class Params:
+    nside: int = 2
+    n_radial: int = 0         # >0: that many evaluation points; 0: from eta_r
+    eta_r: float = 2.0
+    theta: float = 0.5
+    alpha_b: float = ALPHA_B
+    subsample: int = 4
+    zeta_g: bool = True
+    eps_lim: float = 1e-2
+    max_iter: int = 30
+
+
+@dataclass
+class Problem:
+    name: str
+    domains: List[Domain]
+    n_h: List[np.ndarray]              # per domain, float64 [n_cells]
+    src_xyz: List[np.ndarray]          # per domain, float64 [n_src, 3] in cm
+    src_q: List[np.ndarray]            # per domain, float64 [n_src] photons/s
+    params: Params = field(default_factory=Params)
+
+    def total_cells(self) -> int:
+        return sum(d.n_cells() for d in self.domains)
+
+
+def rng_for(*key) -> np.random.Generator:
+    return np.random.default_rng([2105, 9644, *key])
+
+
+def uniform_domain(n: int, box_pc: float = BOX_PC) -> Domain:
+    if n % BLOCK:
+        raise ValueError("grid size must be a multiple of 8")
+    nb = n // BLOCK
+    return Domain(nroot=(nb, nb, nb), root_block_cm=box_pc * PC_CM / nb)
+
+
+def lognormal_field(n: int, sigma: float, mean: float, rng: np.random.Generator) -> np.ndarray:
+    """Log-normal density with a P(k) ~ k^-4 Gaussian random field underneath.
+
+    Steps: white noise in C order, amplitude |k|^-2 in Fourier space (integer
+    wavenumbers, k = 0 removed), back-transform, standardise, exponentiate with
+    ``sigma`` and rescale to the exact empirical ``mean``.
+    """
+    g0 = rng.standard_normal((n, n, n))
+    gk = np.fft.rfftn(g0)
+    kx = np.fft.fftfreq(n) * n
+    kz = np.fft.rfftfreq(n) * n
+    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    amp = np.zeros_like(k2)
+    nz = k2 > 0
+    amp[nz] = 1.0 / k2[nz]
+    g = np.fft.irfftn(gk * amp, s=(n, n, n), axes=(0, 1, 2))
+    g = (g - g.mean()) / g.std()
+    rho = np.exp(sigma * g)
+    return rho * (mean / rho.mean())
+
+
+def uniform_sources(rng: np.random.Generator, n_src: int, box_cm: float,
+                    logq_lo: float, logq_hi: float):
+    xyz = rng.uniform(0.0, box_cm, size=(n_src, 3))
+    q = 10.0 ** rng.uniform(logq_lo, logq_hi, size=n_src)
+    return xyz, q
+
+
+# --------------------------------------------------------------------------
+# The five workloads
+# --------------------------------------------------------------------------
+
+def config1(thin: bool = False) -> Problem:
+    """Uniform 32^3, n_H = 100, Q = 1e48 at the box centre, N_side 2, 32 points."""
+    n = 32
+    dom = uniform_domain(n)
+    box = BOX_PC * PC_CM
+    p = Params(nside=2, n_radial=32, theta=0.5, alpha_b=0.0 if thin else ALPHA_B)
+    return Problem("uniform32_q1e48_nside2", [dom], [np.full(n ** 3, 100.0)],
+                   [np.array([[box / 2, box / 2, box / 2]])], [np.array([1e48])], p)
+
+
+def config2() -> Problem:
+    """Uniform 64^3, n_H = 100, Q = 1e49 at the box centre, N_side 4, 48 points."""
+    n = 64
+    dom = uniform_domain(n)
+    box = BOX_PC * PC_CM
+    p = Params(nside=4, n_radial=48, theta=0.5)
+    return Problem("uniform64_q1e49_nside4", [dom], [np.full(n ** 3, 100.0)],
+                   [np.array([[box / 2, box / 2, box / 2]])], [np.array([1e49])], p)
+
+
+def config3(n: int = 128) -> Problem:
+    """128^3 log-normal (sigma 1, mean 100), 16 sources, Q in [1e47, 1e50], N_PIX 48."""
+    rng = rng_for(3)
+    dom = uniform_domain(n)
+    nh = lognormal_field(n, 1.0, 100.0, rng).ravel()
+    xyz, q = uniform_sources(rng, 16, BOX_PC * PC_CM, 47.0, 50.0)
+    p = Params(nside=2, n_radial=0, eta_r=2.0, theta=0.5)
+    return Problem(f"lognormal{n}_16src_nside2", [dom], [nh], [xyz], [q], p)
+
+
+def config4(n_domains: int = 64, sizes=(32, 48, 64, 96)) -> Problem:
+    """64 independent log-normal domains of uneven sizes, 1-8 sources each, N_PIX 48."""
+    doms, nhs, xyzs, qs = [], [], [], []
+    for m in range(n_domains):
+        rng = rng_for(4, m)
+        n = int(rng.choice(np.asarray(sizes)))
+        dom = uniform_domain(n)
+        nh = lognormal_field(n, 1.0, 100.0, rng).ravel()
+        ns = int(rng.integers(1, 9))
+        xyz, q = uniform_sources(rng, ns, BOX_PC * PC_CM, 47.0, 50.0)
+        doms.append(dom); nhs.append(nh); xyzs.append(xyz); qs.append(q)
+    p = Params(nside=2, n_radial=0, eta_r=2.0, theta=0.5)
+    return Problem(f"batched{n_domains}_lognormal_nside2", doms, nhs, xyzs, qs, p)
+
+
+def amr_from_field(field: np.ndarray, nroot: int, max_level: int, threshold: float,
+                   root_block_cm: float):
+    """Block-structured AMR grid over a fine field.
+
+    ``field`` is given at level 1 (twice the root-level resolution).  Level-0
+    cells take the volume average of their 2^3 field cells, level-1 cells the
+    field value, level-2 cells the value of their parent field cell.  A block
+    is refined when the maximum of the field over its footprint exceeds
+    ``threshold``.  Leaf blocks are listed depth first (root blocks in C
+    order, children in (x, y, z) bit order, x the highest bit).
+    """
+    nf = field.shape[0]
+    assert nf == nroot * BLOCK * 2
+    blocks = []
+    values = []
+
+    def footprint(level, bi, bj, bk):
+        # field cells covered by the block
+        s = BLOCK * 2 // (2 ** level) if level <= 1 else None
+        if level <= 1:
+            return field[bi * s:(bi + 1) * s, bj * s:(bj + 1) * s, bk * s:(bk + 1) * s]
+        # level-2 block: 8 level-2 cells = 4 field cells per axis
+        s2 = BLOCK // 2
+        return field[bi * s2:(bi + 1) * s2, bj * s2:(bj + 1) * s2, bk * s2:(bk + 1) * s2]
+
+    def cells(level, bi, bj, bk):
+        fp = footprint(level, bi, bj, bk)
+        if level == 0:
+            return fp.reshape(BLOCK, 2, BLOCK, 2, BLOCK, 2).mean(axis=(1, 3, 5))
+        if level == 1:
+            return fp
+        return np.repeat(np.repeat(np.repeat(fp, 2, 0), 2, 1), 2, 2)
+
+    def visit(level, bi, bj, bk):
+        fp = footprint(level, bi, bj, bk)
+        if level < max_level and fp.max() > threshold:
+            for c in range(8):
+                cx, cy, cz = (c >> 2) & 1, (c >> 1) & 1, c & 1
+                visit(level + 1, 2 * bi + cx, 2 * bj + cy, 2 * bk + cz)
+        else:
+            blocks.append((level, bi, bj, bk))
+            values.append(cells(level, bi, bj, bk).ravel())
+
+    for bi in range(nroot):
+        for bj in range(nroot):
+            for bk in range(nroot):
+                visit(0, bi, bj, bk)
+    dom = Domain(nroot=(nroot, nroot, nroot), root_block_cm=root_block_cm,
+                 max_level=max_level, leaf_blocks=np.asarray(blocks, dtype=np.int32))
+    return dom, np.concatenate(values)
+
+
+def config5(nroot: int = 16, n_sources: int = 1000) -> Problem:
+    """Adaptive grid: 128^3 base (16^3 root blocks), two refinement levels where
+    n_H > 1e3 on a 256^3 log-normal field (sigma 1.5, mean 100); sources at the
+    centres of distinct finest-level cells with n_H > 1e3, Q in [1e46, 1e49];
+    N_side 4, 64 points."""
+    rng = rng_for(5)
+    nf = nroot * BLOCK * 2
+    field_ = lognormal_field(nf, 1.5, 100.0, rng)
+    box = BOX_PC * PC_CM
+    dom, nh = amr_from_field(field_, nroot, 2, 1e3, box / nroot)
+    # finest-level dense cells
+    lb = dom.leaf_blocks
+    lev = np.repeat(lb[:, 0], BLOCK ** 3)
+    cand = np.nonzero((lev == 2) & (nh > 1e3))[0]
+    pick = rng.choice(cand, size=min(n_sources, cand.size), replace=False)
+    dxf = dom.finest_dx_cm()
+    a = np.arange(BLOCK)
+    ci, cj, ck = np.meshgrid(a, a, a, indexing="ij")
+    off = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)   # C order in block
+    blk = pick // BLOCK ** 3
+    loc = pick % BLOCK ** 3
+    ijk = lb[blk, 1:4].astype(np.int64) * BLOCK + off[loc]        # level-2 cell index
+    xyz = (ijk + 0.5) * dxf
+    q = 10.0 ** rng.uniform(46.0, 49.0, size=pick.size)
+    p = Params(nside=4, n_radial=64, theta=0.5)
+    return Problem("amr256_s1.5_1000src_nside4", [dom], [nh], [xyz], [q], p)
+
+
+def small_uniform(n: int, n_h: float = 100.0, q: float = 1e48, nside: int = 2,
+                  n_radial: int = 0, theta: float = 0.5, centre: bool = True,
+                  seed: int = 0) -> Problem:
+    """Small uniform box (side 4 pc) with one source; for tests."""
+    dom = uniform_domain(n)
+    box = BOX_PC * PC_CM
+    if centre:
+        xyz = np.array([[box / 2, box / 2, box / 2]])
+    else:
+        xyz = rng_for(99, seed).uniform(0, box, size=(1, 3))
+    p = Params(nside=nside, n_radial=n_radial, theta=theta)
+    return Problem(f"uniform{n}", [dom], [np.full(n ** 3, n_h)], [xyz], [np.array([q])], p)
+
+
+def small_lognormal(n: int, n_src: int = 3, sigma: float = 1.0, nside: int = 2,
+                    theta: float = 0.5, n_radial: int = 0, seed: int = 0) -> Problem:
+    """Small log-normal box with random sources; for parity tests."""
+    rng = rng_for(98, seed)
+    dom = uniform_domain(n)
+    nh = lognormal_field(n, sigma, 100.0, rng).ravel()
+    xyz, q = uniform_sources(rng, n_src, BOX_PC * PC_CM, 47.0, 50.0)
+    p = Params(nside=nside, n_radial=n_radial, theta=theta)
+    return Problem(f"lognormal{n}_{n_src}src", [dom], [nh], [xyz], [q], p)
+
+
+def small_amr(nroot: int = 2, seed: int = 0, threshold: float = 150.0,
+              n_src: int = 3, nside: int = 2) -> Problem:
+    """Small two-level adaptive grid; for tests."""
+    rng = rng_for(97, seed)
+    nf = nroot * BLOCK * 2
+    f = lognormal_field(nf, 1.0, 100.0, rng)
+    box = BOX_PC * PC_CM
+    dom, nh = amr_from_field(f, nroot, 2, threshold, box / nroot)
+    xyz, q = uniform_sources(rng, n_src, box, 47.0, 49.0)
+    p = Params(nside=nside, n_radial=24, theta=0.5)
+    return Problem(f"amr{nroot}_{seed}", [dom], [nh], [xyz], [q], p)
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
