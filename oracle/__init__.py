@@ -74,6 +74,8 @@ def lib():
         L.orc_ang2pix.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double]
         L.orc_pix2vec.argtypes = [C.c_int32, C.c_int64, dp]
         L.orc_ang2pix_many.argtypes = [C.c_int32, C.c_int64, dp, i64p]
+        L.orc_num_threads.restype = C.c_int32
+        L.orc_num_threads.argtypes = []
         L.orc_wp.restype = C.c_double
         L.orc_wp.argtypes = [C.c_double]
         L.orc_wp_weights.argtypes = [C.c_int32, dp, C.c_double, C.c_double, dp]
@@ -267,3 +269,7 @@ def accepted(dom, params, n_h, xyz, q, target, f_prev=None, **over):
         if n <= cap:
             return ls[:n].copy(), mom[:n].copy()
         cap = int(n)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

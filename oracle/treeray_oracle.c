@@ -427,6 +427,15 @@ int64_t orc_ang2pix(int32_t nside, double x, double y, double z)
     return 12 * ns * ns - 2 * ir * (ir + 1) + ip;
 }
 
+int32_t orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void orc_ang2pix_many(int32_t nside, int64_t n, const double *xyz, int64_t *out)
 {
     for (int64_t q = 0; q < n; ++q) out[q] = orc_ang2pix(nside, xyz[3 * q], xyz[3 * q + 1], xyz[3 * q + 2]);

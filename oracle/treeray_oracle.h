@@ -74,6 +74,9 @@ double orc_delta_tot(int64_t n, const double *f_new, const double *f_old, const 
 int orc_deposit(const orc_domain *d, int64_t n_src, const double *src_xyz_cm,
                 const double *src_q, double *ndot_out);
 
+/* OpenMP threads a sweep uses */
+int32_t orc_num_threads(void);
+
 /* ---- pieces exposed for the pin tests ---- */
 int64_t orc_ang2pix(int32_t nside, double x, double y, double z);
 void orc_ang2pix_many(int32_t nside, int64_t n, const double *xyz, int64_t *out);

@@ -1,0 +1,1610 @@
+// TreeRay/OnTheSpot on MI355X (gfx950): device kernels and the C ABI.
+//
+// Steps of one outer iteration (paper Sec. 2):
+//   k_fill / k_deposit     point sources onto the leaf cells (Sec. 2.1, 2.6)
+//   k_cell_quantities      eps, alpha, e of every cell (eqs. os:ems, os:abs, os:erd)
+//   k_reduce_level         FP64 bottom-up node moments, one launch per tree level
+//   k_pack                 node records for the sweep (FP64 or FP32, SoA)
+//   k_sweep                per target: walk + node->ray mapping + per-ray
+//                          On-the-Spot integration + sum over rays (Sec. 2.3-2.5)
+//   k_hist / k_select / k_delta   delta_cell with an exact radix-select median
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "tr_internal.h"
+
+namespace tr {
+
+// moment rows of the FP64 node arrays
+enum { MO_EPS = 0, MO_ALPHA, MO_E, MO_V, MO_MASS, MO_MX, MO_MY, MO_MZ, MO_VX, MO_VY, MO_VZ, MO_COUNT };
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f64(double *p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// a1. Point sources onto leaf cells.  A source coordinate within 1e-9 finest
+// cells of a cell face is moved onto it; the rate is split equally over every
+// leaf cell whose closed cube contains the point.  One thread per source
+// descends the tree from its domain's root.
+// ---------------------------------------------------------------------------
+__global__ void k_deposit(const double *__restrict__ xyz, const double *__restrict__ q,
+                          const int32_t *__restrict__ sdom, int32_t n_src, const DomDev *__restrict__ doms,
+                          const int4 *__restrict__ geo, const int2 *__restrict__ topo, double *ndot,
+                          int32_t *err)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_src) return;
+    const DomDev D = doms[sdom[s]];
+    double u[3];
+    for (int a = 0; a < 3; ++a) {
+        double v = xyz[3 * s + a] / D.dx_cm;
+        const double rn = floor(v + 0.5);
+        if (fabs(v - rn) <= 1e-9) v = rn;
+        u[a] = v;
+    }
+    int stack[160];
+    int sp = 0;
+    stack[sp++] = D.root;
+    int cells[8];
+    int nc = 0;
+    while (sp > 0) {
+        const int n = stack[--sp];
+        const int4 g = geo[n];
+        const double sz = (double)(g.w & kSizeMask);
+        if (!(u[0] >= g.x && u[0] <= g.x + sz && u[1] >= g.y && u[1] <= g.y + sz && u[2] >= g.z &&
+              u[2] <= g.z + sz))
+            continue;
+        const int2 tp = topo[n];
+        if (tp.y == 0) {
+            if (nc < 8) cells[nc] = tp.x;
+            ++nc;
+        } else {
+            if (sp + tp.y > 160) { atomicOr(err, 4); return; }
+            for (int c = 0; c < tp.y; ++c) stack[sp++] = tp.x + c;
+        }
+    }
+    if (nc == 0 || nc > 8 || !(q[s] >= 0.0) || !isfinite(q[s])) {
+        atomicOr(err, 1);
+        return;
+    }
+    const double share = q[s] / (double)nc;
+    for (int c = 0; c < nc; ++c) atomicAdd(&ndot[cells[c]], share);
+}
+
+// ---------------------------------------------------------------------------
+// a2. Cell quantities in internal units (length: finest cell of the domain;
+// rate: rate_unit, a power of two).  s = ndot - alpha_B n^2 dV is netted
+// inside the cell: eps = max(s, 0), alpha = max(-s, 0).  E = F_prev dV.
+// ---------------------------------------------------------------------------
+__global__ void k_cell_quantities(int64_t n_cells, const double *__restrict__ n_h,
+                                  const double *__restrict__ ndot, const double *__restrict__ f_prev,
+                                  const int32_t *__restrict__ cell_node, const int32_t *__restrict__ cell_dom,
+                                  const DomDev *__restrict__ doms, const int4 *__restrict__ geo, int32_t thin,
+                                  double *__restrict__ M, int64_t nn, int32_t *err)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int node = cell_node[c];
+    const DomDev D = doms[cell_dom[c]];
+    const int4 g = geo[node];
+    const int sz = g.w & kSizeMask;
+    const double dv = (double)sz * (double)sz * (double)sz;
+    const double nh = n_h[c];
+    double fp = f_prev ? f_prev[c] : 0.0;
+    if (!(nh >= 0.0) || !isfinite(nh) || !(fp >= 0.0) || !isfinite(fp)) {
+        atomicOr(err, 2);
+    }
+    const double s = ndot[c] / D.rate_unit - (thin ? 0.0 : D.alpha_int * nh * nh * dv);
+    const double mass = nh * dv;
+    M[MO_EPS * nn + node] = s > 0.0 ? s : 0.0;
+    M[MO_ALPHA * nn + node] = s < 0.0 ? -s : 0.0;
+    M[MO_E * nn + node] = (fp / D.flux_unit) * dv;
+    M[MO_V * nn + node] = dv;
+    M[MO_MASS * nn + node] = mass;
+    const double cx = g.x + 0.5 * sz, cy = g.y + 0.5 * sz, cz = g.z + 0.5 * sz;
+    M[MO_MX * nn + node] = mass * cx;
+    M[MO_MY * nn + node] = mass * cy;
+    M[MO_MZ * nn + node] = mass * cz;
+    M[MO_VX * nn + node] = dv * cx;
+    M[MO_VY * nn + node] = dv * cy;
+    M[MO_VZ * nn + node] = dv * cz;
+}
+
+// ---------------------------------------------------------------------------
+// a3. Node moments: plain FP64 sums over the children (contiguous), one
+// launch per level, deepest first.
+// ---------------------------------------------------------------------------
+__global__ void k_reduce_level(int64_t b, int64_t e, const int2 *__restrict__ topo, double *__restrict__ M,
+                               int64_t nn)
+{
+    const int64_t n = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= e) return;
+    const int2 tp = topo[n];
+    if (tp.y == 0) return;
+    for (int m = 0; m < MO_COUNT; ++m) {
+        double s = 0.0;
+        const double *row = M + m * nn + tp.x;
+        for (int c = 0; c < tp.y; ++c) s += row[c];
+        M[m * nn + n] = s;
+    }
+}
+
+template <typename R, typename R4>
+__global__ void k_pack(int64_t nn, const double *__restrict__ M, R4 *__restrict__ A, R4 *__restrict__ B)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double m = M[MO_MASS * nn + n], v = M[MO_V * nn + n];
+    double cx, cy, cz;
+    if (m > 0.0) {
+        cx = M[MO_MX * nn + n] / m;
+        cy = M[MO_MY * nn + n] / m;
+        cz = M[MO_MZ * nn + n] / m;
+    } else {
+        cx = M[MO_VX * nn + n] / v;
+        cy = M[MO_VY * nn + n] / v;
+        cz = M[MO_VZ * nn + n] / v;
+    }
+    R4 a, b;
+    a.x = (R)cx; a.y = (R)cy; a.z = (R)cz; a.w = (R)M[MO_EPS * nn + n];
+    b.x = (R)M[MO_ALPHA * nn + n]; b.y = (R)M[MO_E * nn + n]; b.z = (R)v; b.w = (R)0;
+    A[n] = a;
+    B[n] = b;
+}
+
+// ---------------------------------------------------------------------------
+// The sweep
+// ---------------------------------------------------------------------------
+template <typename Real> struct R4T;
+template <> struct R4T<float> { using T = float4; };
+template <> struct R4T<double> { using T = double4; };
+
+struct SweepArgs {
+    const int4 *geo;
+    const int4 *olo;
+    const int4 *oext;
+    const int2 *topo;
+    const void *pA;          // Real4 (com.x, com.y, com.z, eps)
+    const void *pB;          // Real4 (alpha, E, V, 0)
+    const int32_t *cell_node;
+    const int32_t *cell_dom;
+    const DomDev *doms;
+    const double *r64;       // evaluation points, finest-cell units, per domain
+    const float *r32;
+    const int64_t *targets;  // explicit target list, or NULL
+    const int32_t *order;    // all cells in (domain, Morton) order
+    int64_t n_items;
+    int64_t n_cells;
+    double *f_out;
+    uint8_t *ion_out;
+    int32_t *queue;          // [0] next item, [1] overflow flag
+    unsigned long long *stats;  // [0] accepted, [1] tested, [2] guard recomputes
+    void *gbuf;              // ray buffers in global memory (when they do not fit in LDS)
+    double theta2;
+    float guard_tol;
+    int32_t nside, npix, subsample, fmax, nr_max, stride_k, zeta_g;
+};
+
+// ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
+enum { Q_EPS = 0, Q_A = 1, Q_E = 2, Q_V = 3 };
+
+template <typename Real, bool ATOMIC>
+__device__ inline void buf_add(Real *p, Real v)
+{
+    if constexpr (ATOMIC)
+        __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        *p += v;
+}
+
+// Phi (photon rate per steradian) lives in the eps slot of a point once the
+// march has passed it; FP32 buffers keep it as a split double in the
+// (eps, A) slots, both consumed by then.
+__device__ inline double phi_load(double *b, int k, int j, int nrm) { return b[k + Q_EPS * nrm + j]; }
+__device__ inline void phi_store(double *b, int k, int j, int nrm, double v) { b[k + Q_EPS * nrm + j] = v; }
+__device__ inline double phi_load(float *b, int k, int j, int nrm)
+{
+    const uint32_t lo = __float_as_uint(b[k + Q_EPS * nrm + j]);
+    const uint32_t hi = __float_as_uint(b[k + Q_A * nrm + j]);
+    return __hiloint2double((int)hi, (int)lo);
+}
+__device__ inline void phi_store(float *b, int k, int j, int nrm, double v)
+{
+    b[k + Q_EPS * nrm + j] = __uint_as_float((uint32_t)__double2loint(v));
+    b[k + Q_A * nrm + j] = __uint_as_float((uint32_t)__double2hiint(v));
+}
+
+// 1/x in FP64: hardware estimate refined by two Newton steps (x > 0, finite)
+__device__ inline double drcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// One ray (Sec. 2.5): march inwards from the last point, all sources together.
+// Per segment [r_i, r_{i+1}] and source j beyond it:
+//   R = (alpha_i + alpha_{i+1})/2 dV_{i,j} zeta_s zeta_d zeta_g,
+//   zeta_s zeta_d = F_{i+1,j} min(2/F_{i+1}, 1/Fbar_{i+1})   (zeta_d = 2 where Fbar = 0),
+//   dV_{i,j} = (r_{i+1} - r_i)(A^2 + A B + B^2)/3, A = r_j - r_i, B = r_j - r_{i+1},
+// and the source at r_{i+1} itself takes zeta_s = zeta_d = 1.
+// Returns F_{0,k} in internal flux units.
+template <typename Real>
+__device__ double integrate_ray(Real *b, int kbase, const double *r, const double *inv2r, int nr, int nrm, int nside,
+                                int zeta_g)
+{
+    const double inv4pi = 1.0 / (4.0 * kPi);
+    const double ns = (double)nside;
+    uint64_t m0 = 0, m1 = 0;     // points j holding a live Phi_j
+    double a1 = 0.0, fb1 = 0.0;  // alpha and previous flux at r_{i+1}
+    for (int i = nr - 1; i >= 0; --i) {
+        const double Vi = (double)b[kbase + Q_V * nrm + i];
+        double ai = 0.0, fbi = 0.0;
+        if (Vi > 0.0) {
+            const double rv = drcp(Vi);
+            ai = (double)b[kbase + Q_A * nrm + i] * rv;
+            fbi = (double)b[kbase + Q_E * nrm + i] * rv;
+        }
+        const double ei = (double)b[kbase + Q_EPS * nrm + i];
+        if (i <= nr - 2 && (m0 | m1)) {
+            const double ri = r[i], ri1 = r[i + 1], seg = ri1 - ri;
+            // F_{i+1}: flux at r_{i+1} from the sources beyond it
+            double ftot = 0.0;
+            for (int h = 0; h < 2; ++h) {
+                uint64_t m = h ? m1 : m0;
+                while (m) {
+                    const int j = (h << 6) + __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    if (j >= i + 2) {
+                        const double dd = r[j] - ri1;
+                        ftot += phi_load(b, kbase, j, nrm) * drcp(dd * dd);
+                    }
+                }
+            }
+            double g = 0.0;
+            if (ftot > 0.0) {
+                g = 2.0 * drcp(ftot);
+                if (fb1 > 0.0) g = fmin(g, drcp(fb1));
+            }
+            const double aseg = 0.5 * (ai + a1) * seg * (1.0 / 3.0);
+            for (int h = 0; h < 2; ++h) {
+                uint64_t m = h ? m1 : m0;
+                while (m) {
+                    const int j = (h << 6) + __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    double ph = phi_load(b, kbase, j, nrm);
+                    const double rj = r[j];
+                    const double A = rj - ri, B = rj - ri1;
+                    double z = 1.0;
+                    if (j >= i + 2) z = ph * drcp(B * B) * g;
+                    if (zeta_g) z *= fmin(1.0, ns * A * inv2r[j]);
+                    ph = fmax(0.0, ph - aseg * (A * A + A * B + B * B) * z);
+                    phi_store(b, kbase, j, nrm, ph);
+                    if (!(ph > 0.0)) {
+                        if (j < 64) m0 &= ~(1ull << j);
+                        else m1 &= ~(1ull << (j - 64));
+                    }
+                }
+            }
+        }
+        if (i >= 1 && ei > 0.0) {
+            phi_store(b, kbase, i, nrm, ei * inv4pi);
+            if (i < 64) m0 |= 1ull << i;
+            else m1 |= 1ull << (i - 64);
+        }
+        a1 = ai;
+        fb1 = fbi;
+    }
+    double f0 = 0.0;
+    for (int h = 0; h < 2; ++h) {
+        uint64_t m = h ? m1 : m0;
+        while (m) {
+            const int j = (h << 6) + __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const double rj = r[j];
+            f0 += phi_load(b, kbase, j, nrm) * drcp(rj * rj);
+        }
+    }
+    return f0;
+}
+
+// c_magic[n] = ceil(2^16 / n): (l * c_magic[n]) >> 16 == l / n for 0 <= l < 64, 1 <= n <= 64
+__constant__ uint32_t c_magic[65] = {
+    0, 65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554, 5958, 5462, 5042, 4682, 4370, 4096,
+    3856, 3641, 3450, 3277, 3121, 2979, 2850, 2731, 2622, 2521, 2428, 2341, 2260, 2185, 2115, 2048, 1986,
+    1928, 1873, 1821, 1772, 1725, 1681, 1639, 1599, 1561, 1525, 1490, 1457, 1425, 1395, 1366, 1338, 1311,
+    1286, 1261, 1237, 1214, 1192, 1171, 1150, 1130, 1111, 1093, 1075, 1058, 1041, 1024};
+
+template <typename T>
+__device__ inline T rdlane(T v, int l)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    } else {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+        return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    }
+}
+
+// Maps the accepted nodes acc[0..cnt) (cnt <= 64) onto the target's rays;
+// executed by a whole wave in two phases.
+//  Phase 1, lane = node: loads the node, its mass-centre distance d, the
+//   W_p normalisation over the evaluation points in its support and the W_f,3
+//   bracket of its emission (App. A).
+//  Phase 2, lane = angular sub-point, node by node: the pixel of each of the
+//   s^3 sub-box midpoints of the node's box (the share of pixel k is the count
+//   in k over s^3), then the scatter, with lanes covering (pixel, point) pairs.
+// The evaluation points are r_i = c i^2; the per-node loop recomputes them
+// in registers, so it makes no memory round trip besides its atomics.
+template <typename Real, bool ATOMIC>
+__device__ void map_nodes(const SweepArgs &a, Real *buf, const Real *rt, int nr, Real rc_inv, Real rcoef,
+                          const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
+{
+    using R4 = typename R4T<Real>::T;
+    const int lane = lane_id();
+    const Real xe = (Real)0.86602540378443864676;
+    // ---------------- phase 1 ----------------
+    int bx = 0, by = 0, bz = 0, ex = 1, ey = 1, ez = 1, lo = 0, nsup = 0, ie = 1;
+    Real d = 1, hinv = 1, wscale = 0, fb0 = 1, qa = 0, qe = 0, qv = 0, e0 = 0, e1 = 0;
+    if (lane < cnt) {
+        const int n = acc[lane];
+        const int4 g = a.geo[n];
+        const int size = g.w & kSizeMask;
+        bx = g.x; by = g.y; bz = g.z;
+        ex = ey = ez = size;
+        if (g.w & kPartialBit) {
+            const int4 o = a.olo[n], e = a.oext[n];
+            bx = o.x; by = o.y; bz = o.z;
+            ex = e.x; ey = e.y; ez = e.z;
+        }
+        const R4 A = ((const R4 *)a.pA)[n];
+        const R4 B = ((const R4 *)a.pB)[n];
+        qa = B.x; qe = B.y; qv = B.z;
+        const Real dxc = A.x - (Real)0.5 * (Real)tx, dyc = A.y - (Real)0.5 * (Real)ty, dzc = A.z - (Real)0.5 * (Real)tz;
+        d = fsqrt(dxc * dxc + dyc * dyc + dzc * dzc);
+        const Real h = (Real)size;
+        hinv = frcp(h);   // a power of two: exact
+        const Real rl = d - xe * h, rh = d + xe * h;
+        int l0 = rl > (Real)0 ? (int)fsqrt(rl * rc_inv) - 1 : 0;
+        int h0 = (int)fsqrt(rh * rc_inv) + 2;
+        l0 = l0 < 0 ? 0 : l0;
+        h0 = h0 > nr - 1 ? nr - 1 : h0;
+        Real sum = 0;
+        for (int i = l0; i <= h0; ++i) sum += wp_kernel<Real>((rcoef * (Real)(i * i) - d) * hinv);
+        if (sum > (Real)0) {
+            wscale = frcp(sum);
+            lo = l0;
+            nsup = h0 - l0 + 1;
+        } else if (d >= rt[nr - 1]) {   // no point in the support: linear split over the bracket
+            lo = nr - 1;
+            nsup = 1;
+            fb0 = 1;
+        } else {
+            int ib = (int)fsqrt(d * rc_inv);
+            ib = ib > nr - 2 ? nr - 2 : ib;
+            while (ib > 0 && rt[ib] > d) --ib;
+            while (ib < nr - 2 && rt[ib + 1] <= d) ++ib;
+            lo = ib;
+            nsup = 2;
+            fb0 = (rt[ib + 1] - d) * frcp(rt[ib + 1] - rt[ib]);
+        }
+        if (A.w > (Real)0) {   // W_f,3 bracket r_i <= d < r_{i+1}, i >= 1
+            Real u0 = 1, u1 = 0;
+            if (d >= rt[nr - 1]) {
+                ie = nr - 1;
+            } else if (d >= rt[1]) {
+                int k = (int)fsqrt(d * rc_inv);
+                k = k < 1 ? 1 : (k > nr - 2 ? nr - 2 : k);
+                while (k > 1 && rt[k] > d) --k;
+                while (k < nr - 2 && rt[k + 1] <= d) ++k;
+                ie = k;
+                const Real ai = frcp(rt[ie] * rt[ie]), an = frcp(rt[ie + 1] * rt[ie + 1]), ad = frcp(d * d);
+                u0 = (ad - an) * frcp(ai - an);
+                u1 = (Real)1 - u0;
+            }
+            e0 = A.w * u0;
+            e1 = A.w * u1;
+        }
+    }
+
+    // ---------------- phase 2 ----------------
+    const int s = a.subsample, s3 = s * s * s;
+    const int ns = a.nside;
+    const int nrm = a.nr_max;
+    const bool active = lane < s3;
+    const int ia = lane / (s * s), ib = (lane / s) % s, ic = lane % s;
+    const float ca = ((float)ia + 0.5f) + (float)kJit0, cb = ((float)ib + 0.5f) + (float)kJit1,
+                cc = ((float)ic + 0.5f) + (float)kJit2;
+    const float inv_s = 1.0f / (float)s;
+    const Real inv_s3 = (Real)1 / (Real)s3;
+    const uint64_t act_mask = __ballot(active);
+    for (int j = 0; j < cnt; ++j) {
+        const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
+        const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
+        // --- angular ---
+        int pix = 0;
+        if constexpr (sizeof(Real) == 4) {
+            const float vx = fmaf(ca, (float)jex * inv_s, 0.5f * (float)(2 * jbx - tx));
+            const float vy = fmaf(cb, (float)jey * inv_s, 0.5f * (float)(2 * jby - ty));
+            const float vz = fmaf(cc, (float)jez * inv_s, 0.5f * (float)(2 * jbz - tz));
+            bool unsure = false;
+            pix = ang2pix_f(ns, vx, vy, vz, a.guard_tol, unsure);
+            unsure &= active;
+            if (__ballot(unsure)) {
+                if (unsure) {
+                    pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
+                    guard_count += 1.0;
+                }
+            }
+        } else {
+            if (active) pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
+        }
+        pix = pix < 0 ? 0 : (pix >= a.npix ? a.npix - 1 : pix);
+        // --- radial weights: this lane serves support point lo + io of batch slot po ---
+        const int jlo = rdlane(lo, j), jn = rdlane(nsup, j);
+        const Real jd = rdlane(d, j), jhinv = rdlane(hinv, j), jws = rdlane(wscale, j), jfb = rdlane(fb0, j);
+        const Real ja = rdlane(qa, j), je = rdlane(qe, j), jv = rdlane(qv, j);
+        const Real je0 = rdlane(e0, j), je1 = rdlane(e1, j);
+        const int jie = rdlane(ie, j);
+        const bool has_eps = je0 != (Real)0 || je1 != (Real)0;
+        const int span = jn < 64 ? jn : 64;                         // points per batch slot
+        const int G = 64 / span;                                    // pixels per batch
+        // lane / span: (lane + 1/2)/span is at least 1/128 away from an integer
+        const int po = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)span));
+        const int io = lane - po * span;
+        const bool lane_ok = po < G;
+        Real wa = 0, we = 0, wv = 0;
+        if (lane_ok) {
+            Real w;
+            if (jws > (Real)0) {
+                const int i = jlo + io;
+                w = wp_kernel<Real>((rcoef * (Real)(i * i) - jd) * jhinv) * jws;
+            } else {
+                w = io == 0 ? jfb : (Real)1 - jfb;
+            }
+            wa = w * ja;
+            we = w * je;
+            wv = w * jv;
+        }
+        const int col = Q_A * nrm + jlo + io;
+        // --- distinct pixels; scattered in batches of G ---
+        uint64_t rem = act_mask;
+        int q = 0, myk = -1;
+        Real myw = 0;
+        while (rem) {
+            const int first = __ffsll((unsigned long long)rem) - 1;
+            const int k = __builtin_amdgcn_readlane(pix, first);
+            const uint64_t m = __ballot(pix == k) & rem;
+            rem &= ~m;
+            const Real wk = (Real)__popcll(m) * inv_s3;
+            if (po == q) {
+                myk = k;
+                myw = wk;
+            }
+            if (has_eps && lane < 2) {
+                const Real ev = lane == 0 ? je0 : je1;
+                if (ev != (Real)0)
+                    buf_add<Real, ATOMIC>(buf + (size_t)k * a.stride_k + Q_EPS * nrm + jie + lane, wk * ev);
+            }
+            if (jn > 64) {
+                // support wider than a wave (N_R > 64): the remaining points of this pixel
+                Real *row = buf + (size_t)k * a.stride_k + Q_A * nrm + jlo;
+                for (int i2 = 64 + lane; i2 < jn; i2 += 64) {
+                    const int i = jlo + i2;
+                    const Real w2 = jws > (Real)0 ? wp_kernel<Real>((rcoef * (Real)(i * i) - jd) * jhinv) * jws : (Real)0;
+                    buf_add<Real, ATOMIC>(row + i2, wk * w2 * ja);
+                    buf_add<Real, ATOMIC>(row + nrm + i2, wk * w2 * je);
+                    buf_add<Real, ATOMIC>(row + 2 * nrm + i2, wk * w2 * jv);
+                }
+            }
+            ++q;
+            if (q == G || rem == 0) {
+                if (lane_ok && myk >= 0) {
+                    Real *row = buf + (size_t)myk * a.stride_k + col;
+                    buf_add<Real, ATOMIC>(row, myw * wa);
+                    buf_add<Real, ATOMIC>(row + nrm, myw * we);
+                    buf_add<Real, ATOMIC>(row + 2 * nrm, myw * wv);
+                }
+                q = 0;
+                myk = -1;
+            }
+        }
+    }
+}
+
+template <typename Real, int WAVES, bool LDSBUF>
+__global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
+{
+    using R4 = typename R4T<Real>::T;
+    constexpr bool ATOMIC = WAVES > 1;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar loops over waves' work
+    const int nrm = a.nr_max, npix = a.npix;
+    const size_t buf_elems = (size_t)npix * a.stride_k;
+    char *p = smem;
+    Real *buf;
+    if constexpr (LDSBUF) {
+        buf = (Real *)p;
+        p += ((buf_elems * sizeof(Real) + 15) / 16) * 16;
+    } else {
+        buf = (Real *)a.gbuf + (size_t)blockIdx.x * buf_elems;
+    }
+    Real *rt = (Real *)p;
+    p += ((nrm * sizeof(Real) + 15) / 16) * 16;
+    Real *wself = (Real *)p;
+    p += ((nrm * sizeof(Real) + 15) / 16) * 16;
+    double *rd = (double *)p;   // the evaluation points in FP64 for the integration
+    p += nrm * sizeof(double);
+    double *rd2 = (double *)p;  // 1 / (2 r_i)
+    p += nrm * sizeof(double);
+    int *fr0 = (int *)p;
+    p += a.fmax * sizeof(int);
+    int *fr1 = (int *)p;
+    p += a.fmax * sizeof(int);
+    int *acc = (int *)p;
+    p += a.fmax * sizeof(int);
+    int *sc = (int *)p;        // 0 item, 1 nfr, 2 nnext, 3 nacc, 4 overflow
+    p += 16 * sizeof(int);
+    double *red = (double *)p;
+
+    double n_acc = 0, n_test = 0, n_guard = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            sc[0] = atomicAdd(&a.queue[0], 1);
+            sc[4] = 0;
+        }
+        __syncthreads();
+        const int64_t item = sc[0];
+        if (item >= a.n_items) break;
+        const int64_t cell = a.targets ? a.targets[item] : (int64_t)a.order[item];
+        if (cell < 0 || cell >= a.n_cells) {
+            if (tid == 0) {
+                a.f_out[item] = __longlong_as_double(0x7ff8000000000000ll);
+                if (a.ion_out) a.ion_out[item] = 0;
+                atomicOr(&a.queue[1], 2);
+            }
+            continue;
+        }
+        const int dom = a.cell_dom[cell];
+        const DomDev D = a.doms[dom];
+        const int nr = D.nr;
+        const int tnode = a.cell_node[cell];
+        const int4 tg = a.geo[tnode];
+        const int tsize = tg.w & kSizeMask;
+        // doubled target centre: exact integers
+        const int tx = 2 * tg.x + tsize, ty = 2 * tg.y + tsize, tz = 2 * tg.z + tsize;
+        const R4 tA = ((const R4 *)a.pA)[tnode];
+        const R4 tB = ((const R4 *)a.pB)[tnode];
+        const Real rc_inv = (Real)D.rc_inv;
+        const Real rcoef = (Real)(1.0 / D.rc_inv);
+
+        // evaluation points and the self-term weights (W_p at d = 0, h = cell size)
+        for (int i = tid; i < nr; i += WAVES * 64) {
+            const double rv = a.r64[D.r_off + i];
+            rd[i] = rv;
+            rd2[i] = i > 0 ? 1.0 / (2.0 * rv) : 0.0;
+            if constexpr (sizeof(Real) == 4) rt[i] = a.r32[D.r_off + i];
+            else rt[i] = (Real)rv;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            Real w0 = 0, w1 = 0;
+            if (lane < nr) w0 = wp_kernel<Real>(rt[lane] / (Real)tsize);
+            if (lane + 64 < nr) w1 = wp_kernel<Real>(rt[lane + 64] / (Real)tsize);
+            const Real sum = wave_sum(w0 + w1);
+            if (lane < nr) wself[lane] = w0 / sum;
+            if (lane + 64 < nr) wself[lane + 64] = w1 / sum;
+            if (lane == 0) {
+                sc[1] = 1;
+                fr0[0] = D.root;
+            }
+        }
+        __syncthreads();
+        // ray buffer: zero emission, the target's own share of A, E, V
+        {
+            const Real inv_npix = (Real)1 / (Real)npix;
+            const size_t rows = (size_t)npix * 4;
+            for (size_t q = wave; q < rows; q += WAVES) {
+                const int k = (int)(q >> 2), row = (int)(q & 3);
+                Real *dst = buf + (size_t)k * a.stride_k + row * nrm;
+                const Real mom = row == Q_A ? tB.x : row == Q_E ? tB.y : tB.z;
+                for (int i = lane; i < nr; i += 64)
+                    dst[i] = row == Q_EPS ? (Real)0 : mom * (wself[i] * inv_npix);
+            }
+        }
+        __syncthreads();
+
+        // --- level-synchronous walk; accepted nodes mapped after each level ---
+        int *cur = fr0, *nxt = fr1;
+        for (;;) {
+            const int nfr = sc[1];
+            if (nfr == 0 || sc[4]) break;
+            if (tid == 0) {
+                sc[2] = 0;
+                sc[3] = 0;
+            }
+            __syncthreads();
+            for (int base = wave * 64; base < nfr; base += WAVES * 64) {
+                const int idx = base + lane;
+                const bool valid = idx < nfr;
+                int n = 0, nch = 0, fc = 0;
+                bool acc_it = false, open_it = false;
+                if (valid) {
+                    n = cur[idx];
+                    const int4 g = a.geo[n];
+                    const int2 tp = a.topo[n];
+                    const int sz = g.w & kSizeMask;
+                    const bool leaf = tp.y == 0;
+                    const bool inside = (2 * g.x <= tx && tx < 2 * (g.x + sz)) && (2 * g.y <= ty && ty < 2 * (g.y + sz)) &&
+                                        (2 * g.z <= tz && tz < 2 * (g.z + sz));
+                    if (inside) {
+                        open_it = !leaf;
+                    } else if (leaf) {
+                        acc_it = true;
+                    } else {
+                        const double ddx = (double)(2 * g.x + sz - tx), ddy = (double)(2 * g.y + sz - ty),
+                                     ddz = (double)(2 * g.z + sz - tz);
+                        const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                        const double H2 = 4.0 * (double)sz * (double)sz;
+                        acc_it = a.theta2 * D2 > H2;
+                        open_it = !acc_it;
+                    }
+                    nch = open_it ? tp.y : 0;
+                    fc = tp.x;
+                }
+                n_test += valid ? 1.0 : 0.0;
+                const uint64_t macc = __ballot(acc_it);
+                const int nacc_w = __popcll(macc);
+                int tot = 0;
+                const int off = wave_excl_scan(nch, tot);
+                int base_acc = 0, base_fr = 0;
+                if (lane == 0) {
+                    if (nacc_w) base_acc = atomicAdd(&sc[3], nacc_w);
+                    if (tot) base_fr = atomicAdd(&sc[2], tot);
+                }
+                base_acc = __shfl(base_acc, 0, 64);
+                base_fr = __shfl(base_fr, 0, 64);
+                if (base_acc + nacc_w > a.fmax || base_fr + tot > a.fmax) {
+                    if (lane == 0) sc[4] = 1;
+                } else {
+                    if (acc_it) {
+                        const int pos = __popcll(macc & ((1ull << lane) - 1ull));
+                        acc[base_acc + pos] = n;
+                    }
+                    for (int c = 0; c < nch; ++c) nxt[base_fr + off + c] = fc + c;
+                }
+            }
+            __syncthreads();
+            if (sc[4]) break;
+            const int nacc = sc[3];
+            n_acc += (wave == 0 && lane == 0) ? (double)nacc : 0.0;
+            {
+                // contiguous chunks of at most 64 nodes, spread evenly over the waves
+                const int per = (nacc + WAVES - 1) / WAVES;
+                const int b0 = wave * per, b1 = min(nacc, b0 + per);
+                for (int q = b0; q < b1; q += 64)
+                    map_nodes<Real, ATOMIC>(a, buf, rt, nr, rc_inv, rcoef, acc + q, min(64, b1 - q), tx, ty, tz, n_guard);
+            }
+            __syncthreads();
+            if (tid == 0) sc[1] = sc[2];
+            int *t = cur;
+            cur = nxt;
+            nxt = t;
+            __syncthreads();
+        }
+        if (sc[4]) {
+            if (tid == 0) {
+                const int64_t o = a.targets ? item : cell;
+                a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
+                if (a.ion_out) a.ion_out[o] = 0;
+                atomicOr(&a.queue[1], 1);
+            }
+            continue;
+        }
+        __syncthreads();
+
+        // --- per-ray integration and the sum over rays ---
+        // rays spread over all waves: ray k on wave k % WAVES
+        double fsum = 0.0;
+        for (int k = lane * WAVES + wave; k < npix; k += 64 * WAVES)
+            fsum += integrate_ray<Real>(buf, k * a.stride_k, rd, rd2, nr, nrm, a.nside, a.zeta_g);
+        fsum = wave_sum(fsum);
+        if (lane == 0) red[wave] = fsum;
+        __syncthreads();
+        if (tid == 0) {
+            double f = 0.0;
+            for (int w = 0; w < WAVES; ++w) f += red[w];
+            const double rtp = 0.5 * (double)tsize;
+            f += 3.0 * (double)tA.w / (4.0 * kPi * rtp * rtp);
+            const int64_t o = a.targets ? item : cell;
+            a.f_out[o] = f * D.flux_unit;
+            if (a.ion_out) a.ion_out[o] = f > 0.0 ? 1 : 0;
+        }
+    }
+    // statistics
+    n_test = wave_sum(n_test);
+    n_guard = wave_sum(n_guard);
+    if (lane == 0) {
+        if (wave == 0 && n_acc > 0) atomicAdd(&a.stats[0], (unsigned long long)n_acc);
+        if (n_test > 0) atomicAdd(&a.stats[1], (unsigned long long)n_test);
+        if (n_guard > 0) atomicAdd(&a.stats[2], (unsigned long long)n_guard);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a9. delta_cell per domain.  The median is the lower median of the domain's
+// previous flux, found exactly by an 8-pass radix select over the IEEE bit
+// patterns (non-negative doubles order like their bits).
+// ---------------------------------------------------------------------------
+__global__ void k_hist(int64_t n_cells, const double *__restrict__ f, const int32_t *__restrict__ cell_dom,
+                       const unsigned long long *__restrict__ prefix, int shift, unsigned int *__restrict__ hist)
+{
+    __shared__ unsigned int h[256];
+    const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t c = b0 + threadIdx.x;
+    const int64_t last = (b0 + blockDim.x - 1 < n_cells ? b0 + blockDim.x - 1 : n_cells - 1);
+    const int dom0 = cell_dom[b0], dom1 = cell_dom[last];
+    const bool one = dom0 == dom1;   // whole block in one domain: count in LDS first
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    if (c < n_cells) {
+        const int dom = cell_dom[c];
+        const unsigned long long key = (unsigned long long)__double_as_longlong(f[c]);
+        const unsigned long long mask = (shift >= 56) ? 0ull : (~0ull << (shift + 8));
+        if ((key & mask) == prefix[dom]) {
+            const unsigned int digit = (unsigned int)((key >> shift) & 255ull);
+            if (one) atomicAdd(&h[digit], 1u);
+            else atomicAdd(&hist[dom * 256 + digit], 1u);
+        }
+    }
+    __syncthreads();
+    if (one)
+        for (int i = threadIdx.x; i < 256; i += blockDim.x)
+            if (h[i]) atomicAdd(&hist[dom0 * 256 + i], h[i]);
+}
+
+__global__ void k_select(int n_dom, int shift, unsigned int *hist, unsigned long long *prefix,
+                         unsigned long long *rank)
+{
+    const int dom = blockIdx.x * blockDim.x + threadIdx.x;
+    if (dom >= n_dom) return;
+    unsigned long long k = rank[dom];
+    unsigned long long cum = 0;
+    int b = 0;
+    for (; b < 256; ++b) {
+        const unsigned int h = hist[dom * 256 + b];
+        if (cum + h > k) break;
+        cum += h;
+    }
+    if (b > 255) b = 255;
+    rank[dom] = k - cum;
+    prefix[dom] |= ((unsigned long long)b) << shift;
+    for (int q = 0; q < 256; ++q) hist[dom * 256 + q] = 0;
+}
+
+__global__ void k_delta(int64_t n_cells, const double *__restrict__ fn, const double *__restrict__ fo,
+                        const int32_t *__restrict__ cell_dom, const unsigned long long *__restrict__ med,
+                        unsigned long long *__restrict__ dmax)
+{
+    __shared__ unsigned long long wmax[16];
+    const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t c = b0 + threadIdx.x;
+    const int64_t last = (b0 + blockDim.x - 1 < n_cells ? b0 + blockDim.x - 1 : n_cells - 1);
+    const int dom0 = cell_dom[b0];
+    const bool one = dom0 == cell_dom[last];
+    unsigned long long key = 0;   // bits of a non-negative double order like the value
+    int dom = dom0;
+    if (c < n_cells) {
+        dom = cell_dom[c];
+        const double m = __longlong_as_double((long long)med[dom]);
+        const double old = fo[c];
+        const double norm = old > m ? old : m;
+        const double diff = fabs(fn[c] - old);
+        double dl;
+        if (norm > 0.0) dl = diff / norm;
+        else dl = diff > 0.0 ? INFINITY : 0.0;
+        if (!(dl == dl)) dl = INFINITY;
+        key = (unsigned long long)__double_as_longlong(dl);
+    }
+    if (!one) {
+        if (c < n_cells) atomicMax(&dmax[dom], key);
+        return;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(key, o, 64);
+        key = y > key ? y : key;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long mx = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = wmax[w] > mx ? wmax[w] : mx;
+        atomicMax(&dmax[dom0], mx);
+    }
+}
+
+}  // namespace tr
+
+// ===========================================================================
+// Host side: the context and the C ABI
+// ===========================================================================
+using namespace tr;
+
+struct tr_ctx {
+    tr_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int n_cu = 0;
+    std::string err;
+    // domains
+    std::vector<DomTopo> topo;
+    std::vector<DomDev> domh;
+    int32_t n_dom = 0;
+    int64_t n_cells = 0, n_nodes = 0;
+    int32_t depth_max = 0, nr_max = 0;
+    std::vector<int64_t> level_begin;   // global level ranges [L, L+1)
+    // device arrays
+    int4 *geo = nullptr, *olo = nullptr, *oext = nullptr;
+    int2 *topo_d = nullptr;
+    int32_t *cell_node = nullptr, *cell_dom = nullptr, *order = nullptr;
+    DomDev *doms = nullptr;
+    double *r64 = nullptr;
+    float *r32 = nullptr;
+    double *mom = nullptr;
+    void *packA = nullptr, *packB = nullptr;
+    double *ndot = nullptr;
+    // sources
+    std::vector<std::vector<double>> sxyz, sq;
+    double *d_sxyz = nullptr, *d_sq = nullptr;
+    int32_t *d_sdom = nullptr;
+    int32_t n_src_dev = 0;
+    bool src_dirty = true;
+    double rate_unit = 1.0;
+    // sweep state
+    int32_t *queue = nullptr;
+    unsigned long long *stats = nullptr;
+    int32_t *err_flags = nullptr;
+    void *gbuf = nullptr;
+    size_t gbuf_bytes = 0;
+    // delta scratch
+    unsigned int *hist = nullptr;
+    unsigned long long *dprefix = nullptr, *drank = nullptr, *dmax = nullptr;
+    double *solve_tmp = nullptr;
+    int64_t solve_tmp_n = 0;
+    // state
+    bool built = false;
+    tr_precision built_prec = TR_FP64;
+    int32_t waves = 0, tpc = 0, bufmode = 0;   // user launch shape (0 = default)
+    int32_t last_waves = 0, last_tpc = 0, last_lds = 0;
+    int tuned_waves[2] = {0, 0};         // per precision after tr_autotune
+    int tuned_buf[2] = {0, 0};
+    float last_ms = 0.f;
+    bool timed_valid = false;            // ev0/ev1 bracket a recorded sweep
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+tr_status fail(tr_ctx *c, tr_status s, const std::string &m)
+{
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(c, TR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void free_domains(tr_ctx *c)
+{
+    dfree(c->geo); dfree(c->olo); dfree(c->oext); dfree(c->topo_d);
+    dfree(c->cell_node); dfree(c->cell_dom); dfree(c->order); dfree(c->doms);
+    dfree(c->r64); dfree(c->r32); dfree(c->mom); dfree(c->packA); dfree(c->packB);
+    dfree(c->ndot); dfree(c->d_sxyz); dfree(c->d_sq); dfree(c->d_sdom);
+    dfree(c->hist); dfree(c->dprefix); dfree(c->drank); dfree(c->dmax);
+    dfree(c->solve_tmp);
+    dfree(c->gbuf);
+    c->gbuf_bytes = 0;
+    c->solve_tmp_n = 0;
+    c->built = false;
+}
+
+tr_status check_params(tr_ctx *c, const tr_params &p)
+{
+    if (p.nside < 1 || p.nside > 64 || (p.nside & (p.nside - 1))) return fail(c, TR_EINVAL, "nside must be a power of two in [1, 64]");
+    if (p.n_radial < 0 || p.n_radial == 1 || p.n_radial == 2 || p.n_radial > kMaxRadial)
+        return fail(c, TR_EINVAL, "n_radial must be 0 or in [3, 128]");
+    if (p.n_radial == 0 && !(p.eta_r > 0)) return fail(c, TR_EINVAL, "eta_r must be > 0");
+    if (!(p.theta >= 0) || !std::isfinite(p.theta)) return fail(c, TR_EINVAL, "theta must be >= 0");
+    if (!(p.alpha_b >= 0) || !std::isfinite(p.alpha_b)) return fail(c, TR_EINVAL, "alpha_b must be >= 0");
+    if (p.subsample < 1 || p.subsample > 4) return fail(c, TR_EINVAL, "subsample must be in [1, 4]");
+    if (p.max_iter < 0) return fail(c, TR_EINVAL, "max_iter must be >= 0");
+    if (!(p.eps_lim >= 0)) return fail(c, TR_EINVAL, "eps_lim must be >= 0");
+    if (p.precision != TR_FP64 && p.precision != TR_FP32C) return fail(c, TR_EINVAL, "unknown precision");
+    return TR_OK;
+}
+
+inline unsigned grid1(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+tr_status upload(tr_ctx *c, T *&dst, const std::vector<T> &src)
+{
+    dfree(dst);
+    if (src.empty()) return TR_OK;
+    if (hipMalloc((void **)&dst, src.size() * sizeof(T)) != hipSuccess) return fail(c, TR_ENOMEM, "hipMalloc failed");
+    HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return TR_OK;
+}
+
+tr_status dalloc(tr_ctx *c, void **p, size_t bytes)
+{
+    if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) return fail(c, TR_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    return TR_OK;
+}
+
+// LDS bytes of one sweep workgroup (must mirror the carve-up in k_sweep)
+size_t sweep_lds_bytes(size_t real, int npix, int stride_k, int nrm, int fmax, int waves, bool ldsbuf)
+{
+    size_t b = 0;
+    if (ldsbuf) b += (((size_t)npix * stride_k * real + 15) / 16) * 16;
+    b += 2 * (((size_t)nrm * real + 15) / 16) * 16;
+    b += 2 * (size_t)nrm * 8;
+    b += 3 * (size_t)fmax * 4;
+    b += 16 * 4;
+    b += (size_t)waves * 8;
+    return b;
+}
+
+constexpr size_t kLdsMax = 160 * 1024;
+
+using KernelFn = void (*)(SweepArgs);
+
+template <typename Real>
+KernelFn pick_kernel(int waves, bool ldsbuf)
+{
+#define TR_CASE(W)                                                    \
+    case W:                                                           \
+        return ldsbuf ? (KernelFn)k_sweep<Real, W, true> : (KernelFn)k_sweep<Real, W, false>;
+    switch (waves) {
+        TR_CASE(1)
+        TR_CASE(2)
+        TR_CASE(4)
+        TR_CASE(8)
+        TR_CASE(16)
+        default:
+            return nullptr;
+    }
+#undef TR_CASE
+}
+
+struct LaunchPlan {
+    KernelFn fn = nullptr;
+    int waves = 0, blocks = 0, per_cu = 0, fmax = 0, stride_k = 0;
+    size_t lds = 0;
+    bool ldsbuf = true;
+};
+
+tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int buf_req, LaunchPlan &L)
+{
+    const bool f32 = c->p.precision == TR_FP32C;
+    const size_t real = f32 ? 4 : 8;
+    const int npix = 12 * c->p.nside * c->p.nside;
+    const int nrm = c->nr_max;
+    L.stride_k = 4 * nrm + 1;   // odd stride: ray k of lane k hits distinct banks
+    int waves = waves_req;
+    if (waves <= 0) {
+        waves = c->tuned_waves[f32 ? 1 : 0];
+        if (waves <= 0) waves = npix >= 192 ? 8 : 4;
+    }
+    L.waves = waves;
+    L.fmax = 1024;
+    int bm = buf_req > 0 ? buf_req : c->tuned_buf[f32 ? 1 : 0];
+    const bool fits = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, waves, true) <= kLdsMax;
+    if (bm == 1 && !fits) return fail(c, TR_EINVAL, "ray buffers do not fit in LDS for this N_PIX and N_R");
+    L.ldsbuf = bm == 2 ? false : fits;
+    L.lds = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, waves, L.ldsbuf);
+    L.fn = f32 ? pick_kernel<float>(waves, L.ldsbuf) : pick_kernel<double>(waves, L.ldsbuf);
+    if (!L.fn) return fail(c, TR_EINVAL, "waves per target must be 1, 2, 4, 8 or 16");
+    HIPCHK(hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
+    int occ = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)L.fn, waves * 64, L.lds));
+    if (occ <= 0) return fail(c, TR_EINVAL, "sweep kernel does not fit on a compute unit (LDS " + std::to_string(L.lds) + " B)");
+    L.per_cu = tpc_req > 0 ? std::min(tpc_req, occ) : occ;
+    int64_t blocks = (int64_t)c->n_cu * L.per_cu;
+    if (blocks > n_items) blocks = std::max<int64_t>(1, n_items);
+    L.blocks = (int)blocks;
+    if (!L.ldsbuf) {
+        const size_t need = (size_t)L.blocks * npix * L.stride_k * real;
+        if (need > c->gbuf_bytes) {
+            dfree(c->gbuf);
+            c->gbuf_bytes = 0;
+            if (dalloc(c, &c->gbuf, need)) return TR_ENOMEM;
+            c->gbuf_bytes = need;
+        }
+    }
+    return TR_OK;
+}
+
+tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_out, uint8_t *ion, bool timed,
+                       int waves_req, int tpc_req, int buf_req)
+{
+    if (!c->built) return fail(c, TR_ESTATE, "tr_sweep needs tr_build first");
+    if (c->built_prec != c->p.precision) return fail(c, TR_ESTATE, "precision changed since tr_build; build again");
+    if (n == 0) return TR_OK;
+    LaunchPlan L;
+    tr_status s = plan_sweep(c, n, waves_req > 0 ? waves_req : c->waves, tpc_req > 0 ? tpc_req : c->tpc,
+                             buf_req > 0 ? buf_req : c->bufmode, L);
+    if (s) return s;
+    SweepArgs a{};
+    a.geo = c->geo;
+    a.olo = c->olo;
+    a.oext = c->oext;
+    a.topo = c->topo_d;
+    a.pA = c->packA;
+    a.pB = c->packB;
+    a.cell_node = c->cell_node;
+    a.cell_dom = c->cell_dom;
+    a.doms = c->doms;
+    a.r64 = c->r64;
+    a.r32 = c->r32;
+    a.targets = targets;
+    a.order = c->order;
+    a.n_items = n;
+    a.n_cells = c->n_cells;
+    a.f_out = f_out;
+    a.ion_out = ion;
+    a.queue = c->queue;
+    a.stats = c->stats;
+    a.gbuf = c->gbuf;
+    a.theta2 = c->p.theta * c->p.theta;
+    // guard band: 1e-5 N_side (at least 2e-5), several times the worst-case
+    // FP32 error of the pixel-edge quantities (a few 1e-7 N_side)
+    a.guard_tol = 1e-5f * std::max(2.0f, (float)c->p.nside);
+    a.nside = c->p.nside;
+    a.npix = 12 * c->p.nside * c->p.nside;
+    a.subsample = c->p.subsample;
+    a.fmax = L.fmax;
+    a.nr_max = c->nr_max;
+    a.stride_k = L.stride_k;
+    a.zeta_g = c->p.zeta_g;
+    (void)hipGetLastError();   // a stale error of an earlier, unrelated call is not ours
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->queue, (int64_t)2, 0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, c->stats, (int64_t)4);
+    if (timed) HIPCHK(hipEventRecord(c->ev0, c->stream));
+    hipLaunchKernelGGL(L.fn, dim3(L.blocks), dim3(L.waves * 64), L.lds, c->stream, a);
+    HIPCHK(hipGetLastError());
+    if (timed) {
+        HIPCHK(hipEventRecord(c->ev1, c->stream));
+        c->timed_valid = true;
+    }
+    c->last_waves = L.waves;
+    c->last_tpc = L.per_cu;
+    c->last_lds = L.ldsbuf ? 1 : 0;
+    return TR_OK;
+}
+
+tr_status upload_sources(tr_ctx *c)
+{
+    std::vector<double> xyz, q;
+    std::vector<int32_t> dom;
+    double qmax = 0;
+    for (int d = 0; d < c->n_dom; ++d) {
+        for (size_t s = 0; s < c->sq[d].size(); ++s) {
+            for (int a = 0; a < 3; ++a) xyz.push_back(c->sxyz[d][3 * s + a]);
+            q.push_back(c->sq[d][s]);
+            dom.push_back(d);
+            qmax = std::max(qmax, c->sq[d][s]);
+        }
+    }
+    tr_status s;
+    if ((s = upload(c, c->d_sxyz, xyz))) return s;
+    if ((s = upload(c, c->d_sq, q))) return s;
+    if ((s = upload(c, c->d_sdom, dom))) return s;
+    c->n_src_dev = (int32_t)q.size();
+    // internal rate unit: the power of two nearest the largest source rate
+    c->rate_unit = std::ldexp(1.0, (int)std::lround(std::log2(std::max(qmax, 1.0))));
+    for (int d = 0; d < c->n_dom; ++d) {
+        DomDev &D = c->domh[d];
+        D.rate_unit = c->rate_unit;
+        D.flux_unit = c->rate_unit / (D.dx_cm * D.dx_cm);
+        D.alpha_int = c->p.alpha_b * D.dx_cm * D.dx_cm * D.dx_cm / c->rate_unit;
+    }
+    HIPCHK(hipMemcpyAsync(c->doms, c->domh.data(), sizeof(DomDev) * c->n_dom, hipMemcpyHostToDevice, c->stream));
+    c->src_dirty = false;
+    return TR_OK;
+}
+
+tr_status read_flags(tr_ctx *c)
+{
+    int32_t f[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(f, c->err_flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (f[0] & 1) return fail(c, TR_EINVAL, "a source lies outside its domain or has a bad rate");
+    if (f[0] & 2) return fail(c, TR_EINVAL, "n_h or f_prev holds a negative or non-finite value");
+    if (f[0] & 4) return fail(c, TR_EINVAL, "source deposit stack overflow");
+    return TR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tr_status tr_create(tr_ctx **out, const tr_params *p, void *stream)
+{
+    if (!out || !p) return TR_EINVAL;
+    *out = nullptr;
+    tr_ctx *c = new (std::nothrow) tr_ctx();
+    if (!c) return TR_ENOMEM;
+    tr_status s = check_params(c, *p);
+    if (s) {
+        delete c;
+        return s;
+    }
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return TR_EHIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+        delete c;
+        return TR_EHIP;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    if (hipMalloc((void **)&c->queue, 64) != hipSuccess || hipMalloc((void **)&c->stats, 64) != hipSuccess ||
+        hipMalloc((void **)&c->err_flags, 64) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+        hipEventCreate(&c->ev1) != hipSuccess) {
+        tr_destroy(c);
+        return TR_ENOMEM;
+    }
+    // flags and counters start at zero (a sync before any launch reads them)
+    if (hipMemset(c->queue, 0, 64) != hipSuccess || hipMemset(c->stats, 0, 64) != hipSuccess ||
+        hipMemset(c->err_flags, 0, 64) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        tr_destroy(c);
+        return TR_EHIP;
+    }
+    *out = c;
+    return TR_OK;
+}
+
+void tr_destroy(tr_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_domains(c);
+    dfree(c->queue);
+    dfree(c->stats);
+    dfree(c->err_flags);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+const char *tr_last_error(const tr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+tr_status tr_set_domains(tr_ctx *c, int32_t n_domains, const tr_domain *doms)
+{
+    if (!c) return TR_EINVAL;
+    if (n_domains <= 0 || !doms) return fail(c, TR_EINVAL, "need at least one domain");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    free_domains(c);
+    c->topo.assign(n_domains, DomTopo());
+    for (int d = 0; d < n_domains; ++d) {
+        const std::string m = build_topology(doms[d], c->p, c->topo[d]);
+        if (!m.empty()) return fail(c, TR_EINVAL, "domain " + std::to_string(d) + ": " + m);
+    }
+    c->n_dom = n_domains;
+    c->depth_max = 0;
+    c->nr_max = 0;
+    for (auto &t : c->topo) {
+        c->depth_max = std::max(c->depth_max, t.depth);
+        c->nr_max = std::max(c->nr_max, t.n_radial);
+    }
+    // global node numbering: level-major, domains in order inside a level
+    const int L = c->depth_max;
+    std::vector<std::vector<int64_t>> off(L, std::vector<int64_t>(n_domains, 0));
+    std::vector<std::vector<int64_t>> lbase(n_domains);   // local first index of each level
+    c->level_begin.assign(L + 1, 0);
+    int64_t g = 0;
+    for (int l = 0; l < L; ++l) {
+        c->level_begin[l] = g;
+        for (int d = 0; d < n_domains; ++d) {
+            off[l][d] = g;
+            const auto &t = c->topo[d];
+            if (l < t.depth) g += t.level_count[l];
+        }
+    }
+    c->level_begin[L] = g;
+    c->n_nodes = g;
+    for (int d = 0; d < n_domains; ++d) {
+        const auto &t = c->topo[d];
+        int64_t b = 0;
+        for (int l = 0; l < t.depth; ++l) {
+            lbase[d].push_back(b);
+            b += t.level_count[l];
+        }
+    }
+    auto gidx = [&](int d, int64_t local) -> int64_t {
+        const auto &lb = lbase[d];
+        int l = (int)(std::upper_bound(lb.begin(), lb.end(), local) - lb.begin()) - 1;
+        return off[l][d] + (local - lb[l]);
+    };
+    std::vector<int4> geo(g), olo(g), oext(g);
+    std::vector<int2> topo(g);
+    int64_t ncell = 0;
+    for (auto &t : c->topo) ncell += t.n_cells;
+    if (ncell > INT32_MAX) return fail(c, TR_EINVAL, "too many cells");
+    c->n_cells = ncell;
+    std::vector<int32_t> cnode(ncell), cdom(ncell), order(ncell);
+    std::vector<double> r64;
+    std::vector<float> r32;
+    c->domh.assign(n_domains, DomDev());
+    int64_t cbase = 0;
+    for (int d = 0; d < n_domains; ++d) {
+        const auto &t = c->topo[d];
+        const int64_t nn = (int64_t)t.size.size();
+        int64_t first_level_end = t.level_count.empty() ? 0 : 0;
+        (void)first_level_end;
+        for (int64_t i = 0; i < nn; ++i) {
+            const int64_t gi = gidx(d, i);
+            const int32_t sz = t.size[i];
+            bool partial = false;
+            for (int a = 0; a < 3; ++a)
+                if (t.olo[3 * i + a] != t.lo[3 * i + a] || t.oext[3 * i + a] != sz) partial = true;
+            geo[gi] = int4{t.lo[3 * i], t.lo[3 * i + 1], t.lo[3 * i + 2], sz | (partial ? kPartialBit : 0)};
+            olo[gi] = int4{t.olo[3 * i], t.olo[3 * i + 1], t.olo[3 * i + 2], 0};
+            oext[gi] = int4{t.oext[3 * i], t.oext[3 * i + 1], t.oext[3 * i + 2], 0};
+            if (t.nchild[i] == 0) topo[gi] = int2{(int)(cbase + t.first[i]), 0};
+            else topo[gi] = int2{(int)gidx(d, t.first[i]), t.nchild[i]};
+        }
+        for (int64_t q = 0; q < t.n_cells; ++q) {
+            cnode[cbase + q] = (int32_t)gidx(d, t.cell_node[q]);
+            cdom[cbase + q] = d;
+            order[cbase + q] = (int32_t)(cbase + t.morton[q]);
+        }
+        DomDev &D = c->domh[d];
+        D.root = (int32_t)gidx(d, 0);
+        D.nr = t.n_radial;
+        D.r_off = (int32_t)r64.size();
+        D.cell_off = (int32_t)cbase;
+        D.n_cells = (int32_t)t.n_cells;
+        D.dx_cm = t.dx_cm;
+        D.rate_unit = 1.0;
+        D.flux_unit = 1.0 / (t.dx_cm * t.dx_cm);
+        D.alpha_int = c->p.alpha_b * t.dx_cm * t.dx_cm * t.dx_cm;
+        D.rc_inv = 1.0 / t.r_coef;
+        for (double r : t.r_cells) {
+            r64.push_back(r);
+            r32.push_back((float)r);
+        }
+        cbase += t.n_cells;
+    }
+    tr_status s;
+    if ((s = upload(c, c->geo, geo)) || (s = upload(c, c->olo, olo)) || (s = upload(c, c->oext, oext)) ||
+        (s = upload(c, c->topo_d, topo)) || (s = upload(c, c->cell_node, cnode)) ||
+        (s = upload(c, c->cell_dom, cdom)) || (s = upload(c, c->order, order)) || (s = upload(c, c->r64, r64)) ||
+        (s = upload(c, c->r32, r32)) || (s = upload(c, c->doms, c->domh)))
+        return s;
+    if ((s = dalloc(c, (void **)&c->mom, sizeof(double) * MO_COUNT * (size_t)g))) return s;
+    if ((s = dalloc(c, &c->packA, 32 * (size_t)g))) return s;
+    if ((s = dalloc(c, &c->packB, 32 * (size_t)g))) return s;
+    if ((s = dalloc(c, (void **)&c->ndot, sizeof(double) * (size_t)ncell))) return s;
+    if ((s = dalloc(c, (void **)&c->hist, sizeof(unsigned int) * 256 * (size_t)n_domains))) return s;
+    if ((s = dalloc(c, (void **)&c->dprefix, sizeof(unsigned long long) * n_domains))) return s;
+    if ((s = dalloc(c, (void **)&c->drank, sizeof(unsigned long long) * n_domains))) return s;
+    if ((s = dalloc(c, (void **)&c->dmax, sizeof(unsigned long long) * n_domains))) return s;
+    c->sxyz.assign(n_domains, {});
+    c->sq.assign(n_domains, {});
+    c->src_dirty = true;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TR_OK;
+}
+
+tr_status tr_cell_count(const tr_ctx *c, int32_t dom, int64_t *n)
+{
+    if (!c || !n) return TR_EINVAL;
+    if (dom == -1) {
+        *n = c->n_cells;
+        return TR_OK;
+    }
+    if (dom < 0 || dom >= c->n_dom) return TR_EINVAL;
+    *n = c->topo[dom].n_cells;
+    return TR_OK;
+}
+
+tr_status tr_set_sources(tr_ctx *c, int32_t dom, int64_t n, const double *xyz, const double *q)
+{
+    if (!c) return TR_EINVAL;
+    if (dom < 0 || dom >= c->n_dom) return fail(c, TR_EINVAL, "bad domain index");
+    if (n < 0 || (n > 0 && (!xyz || !q))) return fail(c, TR_EINVAL, "bad source arrays");
+    const auto &t = c->topo[dom];
+    for (int64_t s = 0; s < n; ++s) {
+        if (!(q[s] >= 0) || !std::isfinite(q[s])) return fail(c, TR_EINVAL, "source rates must be finite and >= 0");
+        for (int a = 0; a < 3; ++a) {
+            const double u = xyz[3 * s + a] / t.dx_cm;
+            if (!std::isfinite(u) || u < -1e-9 || u > t.ext[a] + 1e-9)
+                return fail(c, TR_EINVAL, "source " + std::to_string(s) + " lies outside domain " + std::to_string(dom));
+        }
+    }
+    c->sxyz[dom].assign(xyz, xyz + 3 * n);
+    c->sq[dom].assign(q, q + n);
+    c->src_dirty = true;
+    c->built = false;
+    return TR_OK;
+}
+
+tr_status tr_build(tr_ctx *c, const double *n_h, const double *f_prev, int32_t thin)
+{
+    if (!c) return TR_EINVAL;
+    if (c->n_dom == 0) return fail(c, TR_ESTATE, "tr_build needs tr_set_domains first");
+    if (!n_h) return fail(c, TR_EINVAL, "n_h is NULL");
+    tr_status s;
+    if (c->src_dirty && (s = upload_sources(c))) return s;
+    const int64_t nn = c->n_nodes, ncell = c->n_cells;
+    (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->err_flags, (int64_t)2, 0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid1(ncell)), dim3(256), 0, c->stream, c->ndot, ncell, 0.0);
+    if (c->n_src_dev > 0)
+        hipLaunchKernelGGL(k_deposit, dim3(grid1(c->n_src_dev, 64)), dim3(64), 0, c->stream, c->d_sxyz, c->d_sq,
+                           c->d_sdom, c->n_src_dev, c->doms, c->geo, c->topo_d, c->ndot, c->err_flags);
+    hipLaunchKernelGGL(k_cell_quantities, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, n_h, c->ndot, f_prev,
+                       c->cell_node, c->cell_dom, c->doms, c->geo, thin, c->mom, nn, c->err_flags);
+    for (int l = c->depth_max - 2; l >= 0; --l) {
+        const int64_t b = c->level_begin[l], e = c->level_begin[l + 1];
+        if (e > b)
+            hipLaunchKernelGGL(k_reduce_level, dim3(grid1(e - b)), dim3(256), 0, c->stream, b, e, c->topo_d, c->mom, nn);
+    }
+    if (c->p.precision == TR_FP32C)
+        hipLaunchKernelGGL((k_pack<float, float4>), dim3(grid1(nn)), dim3(256), 0, c->stream, nn, c->mom, (float4 *)c->packA,
+                           (float4 *)c->packB);
+    else
+        hipLaunchKernelGGL((k_pack<double, double4>), dim3(grid1(nn)), dim3(256), 0, c->stream, nn, c->mom,
+                           (double4 *)c->packA, (double4 *)c->packB);
+    HIPCHK(hipGetLastError());
+    if ((s = read_flags(c))) return s;
+    c->built = true;
+    c->built_prec = c->p.precision;
+    return TR_OK;
+}
+
+tr_status tr_sweep(tr_ctx *c, double *f_out, uint8_t *ion)
+{
+    if (!c) return TR_EINVAL;
+    if (!f_out) return fail(c, TR_EINVAL, "f_out is NULL");
+    return launch_sweep(c, nullptr, c->n_cells, f_out, ion, true, 0, 0, 0);
+}
+
+tr_status tr_sweep_targets(tr_ctx *c, const int64_t *targets, int64_t n, double *f_out, uint8_t *ion)
+{
+    if (!c) return TR_EINVAL;
+    if (n < 0 || (n > 0 && (!targets || !f_out))) return fail(c, TR_EINVAL, "bad target list");
+    return launch_sweep(c, targets, n, f_out, ion, true, 0, 0, 0);
+}
+
+tr_status tr_delta(tr_ctx *c, const double *f_new, const double *f_old, double *delta_host)
+{
+    if (!c) return TR_EINVAL;
+    if (!f_new || !f_old || !delta_host) return fail(c, TR_EINVAL, "NULL argument");
+    if (c->n_dom == 0) return fail(c, TR_ESTATE, "no domains");
+    const int nd = c->n_dom;
+    const int64_t ncell = c->n_cells;
+    (void)hipGetLastError();
+    std::vector<unsigned long long> rank(nd);
+    for (int d = 0; d < nd; ++d) rank[d] = (unsigned long long)((c->topo[d].n_cells - 1) / 2);
+    HIPCHK(hipMemcpyAsync(c->drank, rank.data(), sizeof(unsigned long long) * nd, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(nd)), dim3(256), 0, c->stream, c->dprefix, (int64_t)nd);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(nd)), dim3(256), 0, c->stream, c->dmax, (int64_t)nd);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(256 * nd)), dim3(256), 0, c->stream, (int32_t *)c->hist,
+                       (int64_t)256 * nd, 0);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_hist, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_old, c->cell_dom, c->dprefix,
+                           shift, c->hist);
+        hipLaunchKernelGGL(k_select, dim3(grid1(nd, 64)), dim3(64), 0, c->stream, nd, shift, c->hist, c->dprefix,
+                           c->drank);
+    }
+    hipLaunchKernelGGL(k_delta, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_new, f_old, c->cell_dom,
+                       c->dprefix, c->dmax);
+    HIPCHK(hipGetLastError());
+    std::vector<unsigned long long> dm(nd);
+    HIPCHK(hipMemcpyAsync(dm.data(), c->dmax, sizeof(unsigned long long) * nd, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int d = 0; d < nd; ++d) {
+        double v;
+        std::memcpy(&v, &dm[d], 8);
+        delta_host[d] = v;
+    }
+    return TR_OK;
+}
+
+tr_status tr_solve(tr_ctx *c, const double *n_h, double *f_out, uint8_t *ion, int32_t *iters_out, double *delta_out)
+{
+    if (!c) return TR_EINVAL;
+    if (!n_h || !f_out) return fail(c, TR_EINVAL, "NULL argument");
+    tr_status s;
+    const int64_t ncell = c->n_cells;
+    if (c->solve_tmp_n < ncell) {
+        dfree(c->solve_tmp);
+        if ((s = dalloc(c, (void **)&c->solve_tmp, sizeof(double) * (size_t)ncell))) return s;
+        c->solve_tmp_n = ncell;
+    }
+    if ((s = tr_build(c, n_h, nullptr, 1))) return s;
+    if ((s = tr_sweep(c, f_out, ion))) return s;
+    std::vector<double> dl(c->n_dom, 0.0);
+    int32_t it = 0;
+    double dmax = INFINITY;
+    bool conv = false;
+    while (it < c->p.max_iter) {
+        HIPCHK(hipMemcpyAsync(c->solve_tmp, f_out, sizeof(double) * (size_t)ncell, hipMemcpyDeviceToDevice, c->stream));
+        if ((s = tr_build(c, n_h, c->solve_tmp, 0))) return s;
+        if ((s = tr_sweep(c, f_out, ion))) return s;
+        ++it;
+        if ((s = tr_delta(c, f_out, c->solve_tmp, dl.data()))) return s;
+        dmax = 0;
+        for (double v : dl) dmax = std::max(dmax, v);
+        if (dmax < c->p.eps_lim) {
+            conv = true;
+            break;
+        }
+    }
+    if (iters_out) *iters_out = it;
+    if (delta_out) *delta_out = dmax;
+    if ((s = tr_sync(c))) return s;
+    if (!conv && c->p.max_iter > 0) return fail(c, TR_ENOCONV, "delta_cell did not fall below eps_lim");
+    return TR_OK;
+}
+
+tr_status tr_set_precision(tr_ctx *c, tr_precision prec)
+{
+    if (!c) return TR_EINVAL;
+    if (prec != TR_FP64 && prec != TR_FP32C) return fail(c, TR_EINVAL, "unknown precision");
+    c->p.precision = prec;
+    return TR_OK;
+}
+
+tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer)
+{
+    if (!c) return TR_EINVAL;
+    if (buffer < 0 || buffer > 2) return fail(c, TR_EINVAL, "buffer must be 0 (auto), 1 (LDS) or 2 (device memory)");
+    if (!(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16))
+        return fail(c, TR_EINVAL, "waves per target must be 0, 1, 2, 4, 8 or 16");
+    if (tpc < 0) return fail(c, TR_EINVAL, "targets per CU must be >= 0");
+    c->waves = waves;
+    c->tpc = tpc;
+    c->bufmode = buffer;
+    return TR_OK;
+}
+
+tr_status tr_autotune(tr_ctx *c, double *best_ms)
+{
+    if (!c) return TR_EINVAL;
+    if (!c->built) return fail(c, TR_ESTATE, "tr_autotune needs tr_build first");
+    // sample: every m-th cell in Morton order, enough to fill the chip a few times
+    const int64_t want = std::min<int64_t>(c->n_cells, (int64_t)c->n_cu * 64);
+    const int64_t step = std::max<int64_t>(1, c->n_cells / std::max<int64_t>(1, want));
+    std::vector<int64_t> tg;
+    std::vector<int32_t> ord(c->n_cells);
+    HIPCHK(hipMemcpyAsync(ord.data(), c->order, sizeof(int32_t) * c->n_cells, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < c->n_cells && (int64_t)tg.size() < want; i += step) tg.push_back(ord[i]);
+    int64_t *dt = nullptr;
+    double *fo = nullptr;
+    tr_status s;
+    if ((s = dalloc(c, (void **)&dt, sizeof(int64_t) * tg.size()))) return s;
+    if ((s = dalloc(c, (void **)&fo, sizeof(double) * tg.size()))) { dfree(dt); return s; }
+    HIPCHK(hipMemcpyAsync(dt, tg.data(), sizeof(int64_t) * tg.size(), hipMemcpyHostToDevice, c->stream));
+    const int cand[5] = {1, 2, 4, 8, 16};
+    double best = INFINITY;
+    int bw = 0, bb = 0;
+    for (int bm = 1; bm <= 2; ++bm)
+        for (int w : cand) {
+            LaunchPlan L;
+            if (plan_sweep(c, (int64_t)tg.size(), w, 0, bm, L) != TR_OK) continue;
+            float ms = 0, tot = 0;
+            bool ok = true;
+            for (int rep = 0; rep < 3 && ok; ++rep) {
+                if (launch_sweep(c, dt, (int64_t)tg.size(), fo, nullptr, true, w, 0, bm) != TR_OK) { ok = false; break; }
+                if (hipEventSynchronize(c->ev1) != hipSuccess) { ok = false; break; }
+                (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+                if (rep > 0) tot += ms;
+            }
+            if (ok && tot / 2 < best) {
+                best = tot / 2;
+                bw = w;
+                bb = bm;
+            }
+        }
+    dfree(dt);
+    dfree(fo);
+    c->err.clear();
+    (void)hipGetLastError();
+    if (bw == 0) return fail(c, TR_EHIP, "no launch shape ran");
+    c->tuned_waves[c->p.precision == TR_FP32C ? 1 : 0] = bw;
+    c->tuned_buf[c->p.precision == TR_FP32C ? 1 : 0] = bb;
+    if (best_ms) *best_ms = best;
+    return TR_OK;
+}
+
+tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
+{
+    if (!c || !out) return TR_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    unsigned long long st[4] = {0, 0, 0, 0};
+    int32_t q[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(st, c->stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(q, c->queue, sizeof(q), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out->n_cells = c->n_cells;
+    out->n_nodes = c->n_nodes;
+    out->nodes_accepted = (int64_t)st[0];
+    out->nodes_tested = (int64_t)st[1];
+    out->guard_recomputes = (int64_t)st[2];
+    out->n_radial_max = c->nr_max;
+    out->depth_max = c->depth_max;
+    out->waves_per_target = c->last_waves;
+    out->targets_per_cu = c->last_tpc;
+    out->buffer_in_lds = c->last_lds;
+    out->overflow = q[1];
+    float ms = 0;
+    if (c->timed_valid && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) out->last_sweep_ms = ms;
+    (void)hipGetLastError();
+    return TR_OK;
+}
+
+tr_status tr_sync(tr_ctx *c)
+{
+    if (!c) return TR_EINVAL;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    int32_t q[2] = {0, 0};
+    HIPCHK(hipMemcpy(q, c->queue, sizeof(q), hipMemcpyDeviceToHost));
+    if (q[1] & 2) return fail(c, TR_EINVAL, "a target index lies outside [0, n_cells); those outputs hold NaN");
+    if (q[1]) return fail(c, TR_EOVERFLOW, "a walk list overflowed; affected targets hold NaN");
+    return TR_OK;
+}
+
+}  // extern "C"
