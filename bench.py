@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, help="workload: 1, 2 or 3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=32768, help="oracle targets in the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=98304, help="oracle targets in the CPU baseline")
     ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 

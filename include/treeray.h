@@ -134,6 +134,15 @@ tr_status tr_sweep_targets(tr_ctx *c, const int64_t *targets_dev, int64_t n, dou
  * of |f_new - f_old| / max(f_old, median f_old).  delta_host[n_domains]. */
 tr_status tr_delta(tr_ctx *c, const double *f_new_dev, const double *f_old_dev, double *delta_host);
 
+/* One outer iteration (Sec. 2.5) as a single hipGraph launch: tree build from
+ * n_h_dev and the previous flux f_prev_dev, sweep into f_out_dev (and
+ * ionised_out_dev if not NULL), delta_cell per domain into delta_host
+ * [n_domains].  The graph is captured on the first call and replayed while
+ * the four device pointers, the precision, the launch shape and the sources
+ * stay the same.  f_prev_dev and f_out_dev must differ.  Synchronises. */
+tr_status tr_step(tr_ctx *c, const double *n_h_dev, const double *f_prev_dev, double *f_out_dev,
+                  uint8_t *ionised_out_dev, double *delta_host);
+
 /* Outer iteration (Sec. 2.5): an optically thin build+sweep, then build+sweep
  * with the last flux until every domain has delta_cell < eps_lim or max_iter
  * sweeps.  f_out_dev receives the last flux, iters_out the absorbing sweeps,

@@ -20,7 +20,7 @@ TR_FP64, TR_FP32C = 0, 1
 
 # every entry point of include/treeray.h
 SYMBOLS = ["tr_create", "tr_set_domains", "tr_cell_count", "tr_set_sources", "tr_build", "tr_sweep",
-           "tr_sweep_targets", "tr_delta", "tr_solve", "tr_set_precision", "tr_set_launch", "tr_autotune",
+           "tr_sweep_targets", "tr_delta", "tr_step", "tr_solve", "tr_set_precision", "tr_set_launch", "tr_autotune",
            "tr_get_stats", "tr_sync", "tr_last_error", "tr_destroy"]
 
 
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH):
         "tr_sweep": ([vp, vp, vp], C.c_int),
         "tr_sweep_targets": ([vp, vp, C.c_int64, vp, vp], C.c_int),
         "tr_delta": ([vp, vp, vp, dp], C.c_int),
+        "tr_step": ([vp, vp, vp, vp, vp, dp], C.c_int),
         "tr_solve": ([vp, vp, vp, vp, C.POINTER(C.c_int32), dp], C.c_int),
         "tr_set_precision": ([vp, C.c_int32], C.c_int),
         "tr_set_launch": ([vp, C.c_int32, C.c_int32, C.c_int32], C.c_int),
@@ -184,6 +185,13 @@ class Context:
     def delta(self, f_new, f_old):
         out = np.zeros(self.n_domains)
         self._check(self.L.tr_delta(self.h, _ptr(f_new), _ptr(f_old), out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def step(self, n_h, f_prev, f_out, ion_out=None):
+        """One outer iteration (build, sweep, delta_cell) as a captured hipGraph."""
+        out = np.zeros(self.n_domains)
+        self._check(self.L.tr_step(self.h, _ptr(n_h), _ptr(f_prev), _ptr(f_out), _ptr(ion_out),
+                                   out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
     def solve(self, n_h, f_out, ion_out=None, allow_noconv=False):

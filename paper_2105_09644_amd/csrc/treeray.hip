@@ -208,7 +208,7 @@ struct SweepArgs {
     void *gbuf;              // ray buffers in global memory (when they do not fit in LDS)
     double theta2;
     float guard_tol;
-    int32_t nside, npix, subsample, fmax, nr_max, stride_k, zeta_g;
+    int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
 };
 
 // ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
@@ -542,11 +542,90 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, const Real *rt, int nr,
     }
 }
 
+// LDS flags of the per-target walk (acquire/release inside the workgroup)
+__device__ inline int lds_load(const int *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+// Breadth-first walk of one target by a single wave (Sec. 2.3, 2.4): a node
+// containing the target is opened, every other leaf is accepted, other nodes
+// are accepted when size^2 < theta^2 d^2 (geometric centre, doubled integer
+// coordinates, the product taken in FP64).  Accepted nodes are appended to
+// acc and published through sc[S_AVAIL] as each batch of tests completes, so
+// the other waves map them while the walk goes on.
+enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_COUNT = 16 };
+
+__device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz, int *fr0, int *fr1, int *acc, int *sc,
+                            double &n_test)
+{
+    const int lane = lane_id();
+    int *cur = fr0, *nxt = fr1;
+    if (lane == 0) cur[0] = root;
+    int nfr = 1, nacc = 0;
+    bool ovf = false;
+    while (nfr > 0 && !ovf) {
+        int nn = 0;
+        for (int base = 0; base < nfr; base += 64) {
+            const int idx = base + lane;
+            const bool valid = idx < nfr;
+            int n = 0, nch = 0, fc = 0;
+            bool acc_it = false;
+            if (valid) {
+                n = cur[idx];
+                const int4 g = a.geo[n];
+                const int2 tp = a.topo[n];
+                const int sz = g.w & kSizeMask;
+                const bool leaf = tp.y == 0;
+                const bool inside = (2 * g.x <= tx && tx < 2 * (g.x + sz)) && (2 * g.y <= ty && ty < 2 * (g.y + sz)) &&
+                                    (2 * g.z <= tz && tz < 2 * (g.z + sz));
+                bool open_it = false;
+                if (inside) {
+                    open_it = !leaf;
+                } else if (leaf) {
+                    acc_it = true;
+                } else {
+                    const double ddx = (double)(2 * g.x + sz - tx), ddy = (double)(2 * g.y + sz - ty),
+                                 ddz = (double)(2 * g.z + sz - tz);
+                    const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                    acc_it = a.theta2 * D2 > 4.0 * (double)sz * (double)sz;
+                    open_it = !acc_it;
+                }
+                nch = open_it ? tp.y : 0;
+                fc = tp.x;
+            }
+            n_test += valid ? 1.0 : 0.0;
+            const uint64_t macc = __ballot(acc_it);
+            const int cacc = __popcll(macc);
+            int tot = 0;
+            const int off = wave_excl_scan(nch, tot);
+            if (nacc + cacc > a.amax || nn + tot > a.fmax) {
+                ovf = true;
+                break;
+            }
+            if (acc_it) acc[nacc + __popcll(macc & ((1ull << lane) - 1ull))] = n;
+            for (int c = 0; c < nch; ++c) nxt[nn + off + c] = fc + c;
+            nacc += cacc;
+            nn += tot;
+            if (cacc && lane == 0) lds_store(&sc[S_AVAIL], nacc);
+        }
+        int *t = cur;
+        cur = nxt;
+        nxt = t;
+        nfr = nn;
+    }
+    if (lane == 0) {
+        sc[S_TOTAL] = nacc;
+        if (ovf) sc[S_OVF] = 1;
+        lds_store(&sc[S_AVAIL], nacc);
+        lds_store(&sc[S_DONE], 1);
+    }
+}
+
 template <typename Real, int WAVES, bool LDSBUF>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
 {
     using R4 = typename R4T<Real>::T;
     constexpr bool ATOMIC = WAVES > 1;
+    constexpr int CHUNK = WAVES > 4 ? 16 : 32;   // nodes claimed at a time by a mapping wave
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar loops over waves' work
@@ -573,9 +652,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
     int *fr1 = (int *)p;
     p += a.fmax * sizeof(int);
     int *acc = (int *)p;
-    p += a.fmax * sizeof(int);
-    int *sc = (int *)p;        // 0 item, 1 nfr, 2 nnext, 3 nacc, 4 overflow
-    p += 16 * sizeof(int);
+    p += a.amax * sizeof(int);
+    int *sc = (int *)p;
+    p += S_COUNT * sizeof(int);
     double *red = (double *)p;
 
     double n_acc = 0, n_test = 0, n_guard = 0;
@@ -583,11 +662,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
     for (;;) {
         __syncthreads();
         if (tid == 0) {
-            sc[0] = atomicAdd(&a.queue[0], 1);
-            sc[4] = 0;
+            sc[S_ITEM] = atomicAdd(&a.queue[0], 1);
+            sc[S_AVAIL] = 0;
+            sc[S_CLAIM] = 0;
+            sc[S_DONE] = 0;
+            sc[S_OVF] = 0;
+            sc[S_TOTAL] = 0;
         }
         __syncthreads();
-        const int64_t item = sc[0];
+        const int64_t item = sc[S_ITEM];
         if (item >= a.n_items) break;
         const int64_t cell = a.targets ? a.targets[item] : (int64_t)a.order[item];
         if (cell < 0 || cell >= a.n_cells) {
@@ -627,10 +710,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
             const Real sum = wave_sum(w0 + w1);
             if (lane < nr) wself[lane] = w0 / sum;
             if (lane + 64 < nr) wself[lane + 64] = w1 / sum;
-            if (lane == 0) {
-                sc[1] = 1;
-                fr0[0] = D.root;
-            }
         }
         __syncthreads();
         // ray buffer: zero emission, the target's own share of A, E, V
@@ -647,85 +726,32 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
         }
         __syncthreads();
 
-        // --- level-synchronous walk; accepted nodes mapped after each level ---
-        int *cur = fr0, *nxt = fr1;
+        // --- wave 0 walks; every wave (wave 0 once its walk is done) maps ---
+        if (wave == 0) walk_target(a, D.root, tx, ty, tz, fr0, fr1, acc, sc, n_test);
         for (;;) {
-            const int nfr = sc[1];
-            if (nfr == 0 || sc[4]) break;
-            if (tid == 0) {
-                sc[2] = 0;
-                sc[3] = 0;
-            }
-            __syncthreads();
-            for (int base = wave * 64; base < nfr; base += WAVES * 64) {
-                const int idx = base + lane;
-                const bool valid = idx < nfr;
-                int n = 0, nch = 0, fc = 0;
-                bool acc_it = false, open_it = false;
-                if (valid) {
-                    n = cur[idx];
-                    const int4 g = a.geo[n];
-                    const int2 tp = a.topo[n];
-                    const int sz = g.w & kSizeMask;
-                    const bool leaf = tp.y == 0;
-                    const bool inside = (2 * g.x <= tx && tx < 2 * (g.x + sz)) && (2 * g.y <= ty && ty < 2 * (g.y + sz)) &&
-                                        (2 * g.z <= tz && tz < 2 * (g.z + sz));
-                    if (inside) {
-                        open_it = !leaf;
-                    } else if (leaf) {
-                        acc_it = true;
-                    } else {
-                        const double ddx = (double)(2 * g.x + sz - tx), ddy = (double)(2 * g.y + sz - ty),
-                                     ddz = (double)(2 * g.z + sz - tz);
-                        const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                        const double H2 = 4.0 * (double)sz * (double)sz;
-                        acc_it = a.theta2 * D2 > H2;
-                        open_it = !acc_it;
-                    }
-                    nch = open_it ? tp.y : 0;
-                    fc = tp.x;
+            int start = 0;
+            if (lane == 0) start = atomicAdd(&sc[S_CLAIM], CHUNK);
+            start = __shfl(start, 0, 64);
+            int end = 0;
+            for (;;) {
+                const int avail = lds_load(&sc[S_AVAIL]);
+                if (avail >= start + CHUNK) {
+                    end = start + CHUNK;
+                    break;
                 }
-                n_test += valid ? 1.0 : 0.0;
-                const uint64_t macc = __ballot(acc_it);
-                const int nacc_w = __popcll(macc);
-                int tot = 0;
-                const int off = wave_excl_scan(nch, tot);
-                int base_acc = 0, base_fr = 0;
-                if (lane == 0) {
-                    if (nacc_w) base_acc = atomicAdd(&sc[3], nacc_w);
-                    if (tot) base_fr = atomicAdd(&sc[2], tot);
+                if (lds_load(&sc[S_DONE])) {
+                    const int total = lds_load(&sc[S_TOTAL]);
+                    end = min(start + CHUNK, total);
+                    break;
                 }
-                base_acc = __shfl(base_acc, 0, 64);
-                base_fr = __shfl(base_fr, 0, 64);
-                if (base_acc + nacc_w > a.fmax || base_fr + tot > a.fmax) {
-                    if (lane == 0) sc[4] = 1;
-                } else {
-                    if (acc_it) {
-                        const int pos = __popcll(macc & ((1ull << lane) - 1ull));
-                        acc[base_acc + pos] = n;
-                    }
-                    for (int c = 0; c < nch; ++c) nxt[base_fr + off + c] = fc + c;
-                }
+                __builtin_amdgcn_s_sleep(1);
             }
-            __syncthreads();
-            if (sc[4]) break;
-            const int nacc = sc[3];
-            n_acc += (wave == 0 && lane == 0) ? (double)nacc : 0.0;
-            {
-                // contiguous chunks of at most 64 nodes, spread evenly over the waves
-                const int per = (nacc + WAVES - 1) / WAVES;
-                const int b0 = wave * per, b1 = min(nacc, b0 + per);
-                for (int q = b0; q < b1; q += 64)
-                    map_nodes<Real, ATOMIC>(a, buf, rt, nr, rc_inv, rcoef, acc + q, min(64, b1 - q), tx, ty, tz, n_guard);
-            }
-            __syncthreads();
-            if (tid == 0) sc[1] = sc[2];
-            int *t = cur;
-            cur = nxt;
-            nxt = t;
-            __syncthreads();
+            end = uniform(end);
+            if (end <= start) break;
+            map_nodes<Real, ATOMIC>(a, buf, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz, n_guard);
         }
-        if (sc[4]) {
+        __syncthreads();
+        if (sc[S_OVF]) {
             if (tid == 0) {
                 const int64_t o = a.targets ? item : cell;
                 a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
@@ -734,7 +760,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
             }
             continue;
         }
-        __syncthreads();
+        n_acc += (wave == 0 && lane == 0) ? (double)sc[S_TOTAL] : 0.0;
 
         // --- per-ray integration and the sum over rays ---
         // rays spread over all waves: ray k on wave k % WAVES
@@ -813,6 +839,16 @@ __global__ void k_select(int n_dom, int shift, unsigned int *hist, unsigned long
     rank[dom] = k - cum;
     prefix[dom] |= ((unsigned long long)b) << shift;
     for (int q = 0; q < 256; ++q) hist[dom * 256 + q] = 0;
+}
+
+__global__ void k_rank_init(int n_dom, const DomDev *__restrict__ doms, unsigned long long *rank,
+                            unsigned long long *prefix, unsigned long long *dmax)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n_dom) return;
+    rank[d] = (unsigned long long)((doms[d].n_cells - 1) / 2);   // lower median
+    prefix[d] = 0ull;
+    dmax[d] = 0ull;
 }
 
 __global__ void k_delta(int64_t n_cells, const double *__restrict__ fn, const double *__restrict__ fo,
@@ -913,6 +949,18 @@ struct tr_ctx {
     int tuned_buf[2] = {0, 0};
     float last_ms = 0.f;
     bool timed_valid = false;            // ev0/ev1 bracket a recorded sweep
+    // one outer iteration captured as a hipGraph (tr_step)
+    // (two cached graphs, so that an iteration alternating between two
+    // buffers replays instead of capturing again)
+    struct GraphSlot {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        const void *key[4] = {nullptr, nullptr, nullptr, nullptr};
+        uint64_t used = 0;
+    } gslot[2];
+    uint64_t graph_clock = 0;
+    hipStream_t cap_stream = nullptr;
+    void *pinned = nullptr;              // host copies of the flags and deltas
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -938,8 +986,21 @@ void dfree(T *&p)
     p = nullptr;
 }
 
+void drop_slot(tr_ctx::GraphSlot &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = tr_ctx::GraphSlot();
+}
+
+void drop_graph(tr_ctx *c)
+{
+    for (auto &g : c->gslot) drop_slot(g);
+}
+
 void free_domains(tr_ctx *c)
 {
+    drop_graph(c);
     dfree(c->geo); dfree(c->olo); dfree(c->oext); dfree(c->topo_d);
     dfree(c->cell_node); dfree(c->cell_dom); dfree(c->order); dfree(c->doms);
     dfree(c->r64); dfree(c->r32); dfree(c->mom); dfree(c->packA); dfree(c->packB);
@@ -986,13 +1047,13 @@ tr_status dalloc(tr_ctx *c, void **p, size_t bytes)
 }
 
 // LDS bytes of one sweep workgroup (must mirror the carve-up in k_sweep)
-size_t sweep_lds_bytes(size_t real, int npix, int stride_k, int nrm, int fmax, int waves, bool ldsbuf)
+size_t sweep_lds_bytes(size_t real, int npix, int stride_k, int nrm, int fmax, int amax, int waves, bool ldsbuf)
 {
     size_t b = 0;
     if (ldsbuf) b += (((size_t)npix * stride_k * real + 15) / 16) * 16;
     b += 2 * (((size_t)nrm * real + 15) / 16) * 16;
     b += 2 * (size_t)nrm * 8;
-    b += 3 * (size_t)fmax * 4;
+    b += 2 * (size_t)fmax * 4 + (size_t)amax * 4;
     b += 16 * 4;
     b += (size_t)waves * 8;
     return b;
@@ -1022,7 +1083,7 @@ KernelFn pick_kernel(int waves, bool ldsbuf)
 
 struct LaunchPlan {
     KernelFn fn = nullptr;
-    int waves = 0, blocks = 0, per_cu = 0, fmax = 0, stride_k = 0;
+    int waves = 0, blocks = 0, per_cu = 0, fmax = 0, amax = 0, stride_k = 0;
     size_t lds = 0;
     bool ldsbuf = true;
 };
@@ -1040,12 +1101,18 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
         if (waves <= 0) waves = npix >= 192 ? 8 : 4;
     }
     L.waves = waves;
-    L.fmax = 1024;
+    // per-level frontier and per-target accepted-node capacities (overflow is reported)
+    L.fmax = 512;
+    L.amax = 2048;
     int bm = buf_req > 0 ? buf_req : c->tuned_buf[f32 ? 1 : 0];
-    const bool fits = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, waves, true) <= kLdsMax;
+    const bool fits = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
     if (bm == 1 && !fits) return fail(c, TR_EINVAL, "ray buffers do not fit in LDS for this N_PIX and N_R");
     L.ldsbuf = bm == 2 ? false : fits;
-    L.lds = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, waves, L.ldsbuf);
+    if (!L.ldsbuf) {
+        L.fmax = 1024;
+        L.amax = 4096;
+    }
+    L.lds = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, L.amax, waves, L.ldsbuf);
     L.fn = f32 ? pick_kernel<float>(waves, L.ldsbuf) : pick_kernel<double>(waves, L.ldsbuf);
     if (!L.fn) return fail(c, TR_EINVAL, "waves per target must be 1, 2, 4, 8 or 16");
     HIPCHK(hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
@@ -1107,6 +1174,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.npix = 12 * c->p.nside * c->p.nside;
     a.subsample = c->p.subsample;
     a.fmax = L.fmax;
+    a.amax = L.amax;
     a.nr_max = c->nr_max;
     a.stride_k = L.stride_k;
     a.zeta_g = c->p.zeta_g;
@@ -1220,6 +1288,8 @@ void tr_destroy(tr_ctx *c)
     dfree(c->queue);
     dfree(c->stats);
     dfree(c->err_flags);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -1375,18 +1445,18 @@ tr_status tr_set_sources(tr_ctx *c, int32_t dom, int64_t n, const double *xyz, c
     c->sq[dom].assign(q, q + n);
     c->src_dirty = true;
     c->built = false;
+    drop_graph(c);
     return TR_OK;
 }
 
-tr_status tr_build(tr_ctx *c, const double *n_h, const double *f_prev, int32_t thin)
+}  // extern "C"
+
+namespace {
+
+// Enqueues the tree build (no host synchronisation; capturable).
+tr_status enqueue_build(tr_ctx *c, const double *n_h, const double *f_prev, int32_t thin)
 {
-    if (!c) return TR_EINVAL;
-    if (c->n_dom == 0) return fail(c, TR_ESTATE, "tr_build needs tr_set_domains first");
-    if (!n_h) return fail(c, TR_EINVAL, "n_h is NULL");
-    tr_status s;
-    if (c->src_dirty && (s = upload_sources(c))) return s;
     const int64_t nn = c->n_nodes, ncell = c->n_cells;
-    (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->err_flags, (int64_t)2, 0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid1(ncell)), dim3(256), 0, c->stream, c->ndot, ncell, 0.0);
     if (c->n_src_dev > 0)
@@ -1406,6 +1476,50 @@ tr_status tr_build(tr_ctx *c, const double *n_h, const double *f_prev, int32_t t
         hipLaunchKernelGGL((k_pack<double, double4>), dim3(grid1(nn)), dim3(256), 0, c->stream, nn, c->mom,
                            (double4 *)c->packA, (double4 *)c->packB);
     HIPCHK(hipGetLastError());
+    return TR_OK;
+}
+
+// Enqueues delta_cell per domain into c->dmax (capturable).
+tr_status enqueue_delta(tr_ctx *c, const double *f_new, const double *f_old)
+{
+    const int nd = c->n_dom;
+    const int64_t ncell = c->n_cells;
+    hipLaunchKernelGGL(k_rank_init, dim3(grid1(nd, 64)), dim3(64), 0, c->stream, nd, c->doms, c->drank, c->dprefix,
+                       c->dmax);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(256 * nd)), dim3(256), 0, c->stream, (int32_t *)c->hist,
+                       (int64_t)256 * nd, 0);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_hist, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_old, c->cell_dom, c->dprefix,
+                           shift, c->hist);
+        hipLaunchKernelGGL(k_select, dim3(grid1(nd, 64)), dim3(64), 0, c->stream, nd, shift, c->hist, c->dprefix,
+                           c->drank);
+    }
+    hipLaunchKernelGGL(k_delta, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_new, f_old, c->cell_dom,
+                       c->dprefix, c->dmax);
+    HIPCHK(hipGetLastError());
+    return TR_OK;
+}
+
+tr_status check_build_args(tr_ctx *c, const double *n_h)
+{
+    if (c->n_dom == 0) return fail(c, TR_ESTATE, "tr_build needs tr_set_domains first");
+    if (!n_h) return fail(c, TR_EINVAL, "n_h is NULL");
+    tr_status s;
+    if (c->src_dirty && (s = upload_sources(c))) return s;
+    return TR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tr_status tr_build(tr_ctx *c, const double *n_h, const double *f_prev, int32_t thin)
+{
+    if (!c) return TR_EINVAL;
+    tr_status s;
+    if ((s = check_build_args(c, n_h))) return s;
+    (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+    if ((s = enqueue_build(c, n_h, f_prev, thin))) return s;
     if ((s = read_flags(c))) return s;
     c->built = true;
     c->built_prec = c->p.precision;
@@ -1431,33 +1545,84 @@ tr_status tr_delta(tr_ctx *c, const double *f_new, const double *f_old, double *
     if (!c) return TR_EINVAL;
     if (!f_new || !f_old || !delta_host) return fail(c, TR_EINVAL, "NULL argument");
     if (c->n_dom == 0) return fail(c, TR_ESTATE, "no domains");
-    const int nd = c->n_dom;
-    const int64_t ncell = c->n_cells;
     (void)hipGetLastError();
-    std::vector<unsigned long long> rank(nd);
-    for (int d = 0; d < nd; ++d) rank[d] = (unsigned long long)((c->topo[d].n_cells - 1) / 2);
-    HIPCHK(hipMemcpyAsync(c->drank, rank.data(), sizeof(unsigned long long) * nd, hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(nd)), dim3(256), 0, c->stream, c->dprefix, (int64_t)nd);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(nd)), dim3(256), 0, c->stream, c->dmax, (int64_t)nd);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(256 * nd)), dim3(256), 0, c->stream, (int32_t *)c->hist,
-                       (int64_t)256 * nd, 0);
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_hist, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_old, c->cell_dom, c->dprefix,
-                           shift, c->hist);
-        hipLaunchKernelGGL(k_select, dim3(grid1(nd, 64)), dim3(64), 0, c->stream, nd, shift, c->hist, c->dprefix,
-                           c->drank);
-    }
-    hipLaunchKernelGGL(k_delta, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_new, f_old, c->cell_dom,
-                       c->dprefix, c->dmax);
-    HIPCHK(hipGetLastError());
+    tr_status s;
+    if ((s = enqueue_delta(c, f_new, f_old))) return s;
+    const int nd = c->n_dom;
     std::vector<unsigned long long> dm(nd);
     HIPCHK(hipMemcpyAsync(dm.data(), c->dmax, sizeof(unsigned long long) * nd, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    for (int d = 0; d < nd; ++d) {
-        double v;
-        std::memcpy(&v, &dm[d], 8);
-        delta_host[d] = v;
+    for (int d = 0; d < nd; ++d) std::memcpy(&delta_host[d], &dm[d], 8);
+    return TR_OK;
+}
+
+tr_status tr_step(tr_ctx *c, const double *n_h, const double *f_prev, double *f_out, uint8_t *ion, double *delta_host)
+{
+    if (!c) return TR_EINVAL;
+    if (!f_prev || !f_out || !delta_host) return fail(c, TR_EINVAL, "NULL argument");
+    if (f_prev == f_out) return fail(c, TR_EINVAL, "f_prev and f_out must be different buffers");
+    tr_status s;
+    if ((s = check_build_args(c, n_h))) return s;
+    const int nd = c->n_dom;
+    const void *key[4] = {n_h, f_prev, f_out, ion};
+    tr_ctx::GraphSlot *slot = nullptr;
+    for (auto &g : c->gslot) {
+        bool same = g.exec != nullptr;
+        for (int q = 0; q < 4 && same; ++q) same = key[q] == g.key[q];
+        if (same) slot = &g;
     }
+    (void)hipGetLastError();
+    if (!slot) {
+        slot = c->gslot[0].used <= c->gslot[1].used ? &c->gslot[0] : &c->gslot[1];
+        drop_slot(*slot);
+        // plan (and allocate) the sweep before capturing it
+        LaunchPlan L;
+        if ((s = plan_sweep(c, c->n_cells, c->waves, c->tpc, c->bufmode, L))) return s;
+        if (!c->cap_stream) HIPCHK(hipStreamCreate(&c->cap_stream));
+        if (!c->pinned) HIPCHK(hipHostMalloc(&c->pinned, 64 + sizeof(unsigned long long) * (size_t)nd));
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        tr_status cs = enqueue_build(c, n_h, f_prev, 0);
+        const bool built = c->built;
+        const tr_precision bp = c->built_prec;
+        c->built = true;
+        c->built_prec = c->p.precision;
+        if (!cs) cs = launch_sweep(c, nullptr, c->n_cells, f_out, ion, false, 0, 0, 0);
+        c->built = built;
+        c->built_prec = bp;
+        if (!cs) cs = enqueue_delta(c, f_out, f_prev);
+        if (!cs && (hipMemcpyAsync(c->pinned, c->err_flags, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+                    hipMemcpyAsync((char *)c->pinned + 8, c->queue, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess))
+            cs = fail(c, TR_EHIP, "capture of the flag copy failed");
+        if (!cs && hipMemcpyAsync((char *)c->pinned + 64, c->dmax, sizeof(unsigned long long) * (size_t)nd,
+                                  hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+            cs = fail(c, TR_EHIP, "capture of the delta copy failed");
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
+        c->stream = user;
+        if (cs) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs;
+        }
+        if (ee != hipSuccess) return fail(c, TR_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        slot->graph = g;
+        HIPCHK(hipGraphInstantiate(&slot->exec, slot->graph, nullptr, nullptr, 0));
+        for (int q = 0; q < 4; ++q) slot->key[q] = key[q];
+    }
+    slot->used = ++c->graph_clock;
+    HIPCHK(hipGraphLaunch(slot->exec, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->timed_valid = false;   // no timed sweep in a step
+    int32_t flags[4];
+    std::memcpy(flags, c->pinned, 16);
+    if (flags[3]) return fail(c, TR_EOVERFLOW, "a walk list overflowed; affected cells hold NaN");
+    if (flags[0] & 1) return fail(c, TR_EINVAL, "a source lies outside its domain or has a bad rate");
+    if (flags[0] & 2) return fail(c, TR_EINVAL, "n_h or f_prev holds a negative or non-finite value");
+    if (flags[0] & 4) return fail(c, TR_EINVAL, "source deposit stack overflow");
+    for (int d = 0; d < nd; ++d) std::memcpy(&delta_host[d], (char *)c->pinned + 64 + 8 * d, 8);
+    c->built = true;
+    c->built_prec = c->p.precision;
     return TR_OK;
 }
 
@@ -1468,22 +1633,24 @@ tr_status tr_solve(tr_ctx *c, const double *n_h, double *f_out, uint8_t *ion, in
     tr_status s;
     const int64_t ncell = c->n_cells;
     if (c->solve_tmp_n < ncell) {
+        drop_graph(c);
         dfree(c->solve_tmp);
         if ((s = dalloc(c, (void **)&c->solve_tmp, sizeof(double) * (size_t)ncell))) return s;
         c->solve_tmp_n = ncell;
     }
+    // F^0: the optically thin sweep
     if ((s = tr_build(c, n_h, nullptr, 1))) return s;
     if ((s = tr_sweep(c, f_out, ion))) return s;
     std::vector<double> dl(c->n_dom, 0.0);
     int32_t it = 0;
     double dmax = INFINITY;
     bool conv = false;
+    // iterations alternate between f_out and the scratch field; each is one graph launch
+    double *cur = f_out, *nxt = c->solve_tmp;
     while (it < c->p.max_iter) {
-        HIPCHK(hipMemcpyAsync(c->solve_tmp, f_out, sizeof(double) * (size_t)ncell, hipMemcpyDeviceToDevice, c->stream));
-        if ((s = tr_build(c, n_h, c->solve_tmp, 0))) return s;
-        if ((s = tr_sweep(c, f_out, ion))) return s;
+        if ((s = tr_step(c, n_h, cur, nxt, ion, dl.data()))) return s;
+        std::swap(cur, nxt);
         ++it;
-        if ((s = tr_delta(c, f_out, c->solve_tmp, dl.data()))) return s;
         dmax = 0;
         for (double v : dl) dmax = std::max(dmax, v);
         if (dmax < c->p.eps_lim) {
@@ -1491,6 +1658,8 @@ tr_status tr_solve(tr_ctx *c, const double *n_h, double *f_out, uint8_t *ion, in
             break;
         }
     }
+    if (cur != f_out)
+        HIPCHK(hipMemcpyAsync(f_out, cur, sizeof(double) * (size_t)ncell, hipMemcpyDeviceToDevice, c->stream));
     if (iters_out) *iters_out = it;
     if (delta_out) *delta_out = dmax;
     if ((s = tr_sync(c))) return s;
@@ -1502,6 +1671,7 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec)
 {
     if (!c) return TR_EINVAL;
     if (prec != TR_FP64 && prec != TR_FP32C) return fail(c, TR_EINVAL, "unknown precision");
+    if (c->p.precision != prec) drop_graph(c);
     c->p.precision = prec;
     return TR_OK;
 }
@@ -1516,6 +1686,7 @@ tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer)
     c->waves = waves;
     c->tpc = tpc;
     c->bufmode = buffer;
+    drop_graph(c);
     return TR_OK;
 }
 
@@ -1565,6 +1736,7 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
     if (bw == 0) return fail(c, TR_EHIP, "no launch shape ran");
     c->tuned_waves[c->p.precision == TR_FP32C ? 1 : 0] = bw;
     c->tuned_buf[c->p.precision == TR_FP32C ? 1 : 0] = bb;
+    drop_graph(c);
     if (best_ms) *best_ms = best;
     return TR_OK;
 }

@@ -230,6 +230,58 @@ def test_solve_matches_oracle(T, orc):
     ctx.close()
 
 
+def test_graph_step_replays(T, orc):
+    """tr_step (one outer iteration captured as a hipGraph) against the eager
+    build/sweep/delta calls, replayed several times with eager work between
+    the replays, every replay checked; then against the oracle."""
+    P = W.small_lognormal(16, n_src=3, seed=10)
+    f0, _ = orc_sweep(orc, P, thin=True)
+    f1, i1 = orc_sweep(orc, P, f_prev=f0)
+    d_or = orc.delta_cell(f1, f0)
+    # atomic accumulation order differs between launches: FP64 agrees to
+    # rounding, FP32C to its own tolerance away from the front
+    for prec, tol in ((T.TR_FP64, 1e-12), (T.TR_FP32C, TOL32)):
+        ctx = T.context_for(P, prec)
+        n = ctx.n_cells
+        nh = torch.tensor(P.n_h[0], device="cuda")
+        fp = torch.tensor(f0, device="cuda")
+        ref = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.build(nh, fp)
+        ctx.sweep(ref)
+        d_ref = ctx.delta(ref, fp)
+        ref_h = ref.cpu().numpy()
+        ref_ion = (ref_h > 0).astype(np.uint8)
+        fr = None if prec == T.TR_FP64 else front_mask(P, ref_h)
+        out = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ion = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        scratch = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for rep in range(4):
+            out.fill_(-1.0)
+            ion.fill_(7)
+            d = ctx.step(nh, fp, out, ion)
+            g = out.cpu().numpy()
+            log(f"graph prec {prec} replay {rep}: delta {d[0]:.6e} eager {d_ref[0]:.6e}")
+            compare(g, ion.cpu().numpy(), ref_h, ref_ion, tol, front=fr, name=f"replay {rep} vs eager")
+            assert d[0] == pytest.approx(d_ref[0], rel=1e-9 if prec == T.TR_FP64 else 1e-3)
+            # eager work between replays: another build and sweep, a torch kernel
+            ctx.build(nh, thin=True)
+            ctx.sweep(scratch)
+            scratch.mul_(0.5)
+            torch.cuda.synchronize()
+        tol_or = TOL64 if prec == T.TR_FP64 else TOL32
+        compare(out.cpu().numpy(), ion.cpu().numpy(), f1, i1, tol_or,
+                front=None if prec == T.TR_FP64 else front_mask(P, f1), name=f"graph step prec {prec}")
+        assert d[0] == pytest.approx(d_or, rel=1e-9 if prec == T.TR_FP64 else 1e-3)
+        # new buffers: the graph is captured again
+        out2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.step(nh, fp, out2)
+        assert torch.equal(out2 > 0, out > 0)
+        with pytest.raises(T.TreeRayError) as e:
+            ctx.step(nh, fp, fp)
+        assert e.value.status == T.TR_EINVAL
+        ctx.close()
+
+
 def test_errors(T):
     P = W.small_uniform(16)
     ctx = T.context_for(P, T.TR_FP64)
