@@ -6,8 +6,9 @@ per-ray On-the-Spot integration + sum over rays) and delta_cell.  Inputs
 (densities, previous flux) are resident in HBM before the timed region.
 
 The default workload is the uniform 64^3 grid around one Q = 1e49 source
-with N_side 4 (192 rays), theta 0.5 and 48 evaluation points.  The FP32 +
-compensated form is timed for `value`; the FP64 form runs the same steps on
+with N_side 4 (192 rays), theta 0.5 and 48 evaluation points.  The FP32C form
+(FP32 walk, weights and ray buffers; FP64 moments, integration and flux sums)
+is timed for `value`; the FP64 form runs the same steps on
 the same inputs for the speed-up.  The FP64 CPU oracle is timed on a bounded
 sample of targets on the host and gives the reported error of both forms.
 
@@ -230,7 +231,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": P.name, "cells": n_cells, "domains": len(P.domains), "n_pix": npix,
                    "theta": P.params.theta, "n_radial_max": r["nr"],
-                   "precision": ("FP32 walk/weights/ray buffers, FP64 moments and ray integration, compensated sums"
+                   "precision": ("FP32 walk/weights/ray buffers, FP64 moments, ray integration and flux sums"
                                  if main_form == "f32" else "FP64 throughout")},
         "sweep_ms": round(r["sweep_ms"], 3),
         "ms_per_step_graph": round(r["ms_per_step_graph"], 3),

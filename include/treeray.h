@@ -8,7 +8,7 @@
  * every accepted node onto the radial evaluation points of 12 N_side^2
  * HEALPix rays (Sec. 2.2, 2.3, App. A), the On-the-Spot integration of each
  * ray (Sec. 2.5) and the outer iteration with the delta_cell error control
- * (Sec. 2.5 "Iterations and error control").
+ * (Sec. 2.6 "Iterations and error control").
  *
  * Conventions
  *  - All arguments named *_dev are device pointers (HIP memory on the
@@ -52,8 +52,9 @@ typedef enum {
 typedef enum {
     TR_FP64 = 0,        /* FP64 throughout */
     TR_FP32C = 1        /* FP32 walk, angular and radial weights and ray buffers;
-                           FP64 node moments, FP64 ray integration and
-                           compensated flux sums */
+                           FP64 node moments, FP64 ray integration and FP64
+                           flux sums (which stand in for compensated FP32
+                           sums: FP64 vector math runs at the FP32 rate) */
 } tr_precision;
 
 /* One grid: an array of nroot root blocks of 8^3 cells, optionally refined
@@ -107,7 +108,7 @@ tr_status tr_set_domains(tr_ctx *c, int32_t n_domains, const tr_domain *doms);
 tr_status tr_cell_count(const tr_ctx *c, int32_t dom, int64_t *n_cells);
 
 /* Point sources of domain dom: xyz_cm[n][3] relative to the domain's low
- * corner, q[n] photons/s (Sec. 2.6).  Each rate is split equally over the
+ * corner, q[n] photons/s (Sec. 2.7).  Each rate is split equally over the
  * leaf cells whose closed extent contains the point. */
 tr_status tr_set_sources(tr_ctx *c, int32_t dom, int64_t n, const double *xyz_cm,
                          const double *q_per_s);
@@ -122,7 +123,7 @@ tr_status tr_build(tr_ctx *c, const double *n_h_dev, const double *f_prev_dev, i
 /* One sweep over every leaf cell of every domain (Sec. 2.3-2.5): tree walk,
  * node->ray mapping, per-ray integration, sum over rays.  Writes the photon
  * flux f_out_dev[cells] and, if not NULL, ionised_out_dev[cells] = F > 0
- * (Sec. 2.5 "Interaction with gas", option (i)).  Needs tr_build. */
+ * (Sec. 2.6 "Interaction with gas", option (i)).  Needs tr_build. */
 tr_status tr_sweep(tr_ctx *c, double *f_out_dev, uint8_t *ionised_out_dev);
 
 /* The same for a list of global cell indices targets_dev[n] (int64);
@@ -134,7 +135,7 @@ tr_status tr_sweep_targets(tr_ctx *c, const int64_t *targets_dev, int64_t n, dou
  * of |f_new - f_old| / max(f_old, median f_old).  delta_host[n_domains]. */
 tr_status tr_delta(tr_ctx *c, const double *f_new_dev, const double *f_old_dev, double *delta_host);
 
-/* One outer iteration (Sec. 2.5) as a single hipGraph launch: tree build from
+/* One outer iteration (Sec. 2.6) as a single hipGraph launch: tree build from
  * n_h_dev and the previous flux f_prev_dev, sweep into f_out_dev (and
  * ionised_out_dev if not NULL), delta_cell per domain into delta_host
  * [n_domains].  The graph is captured on the first call and replayed while
@@ -143,7 +144,7 @@ tr_status tr_delta(tr_ctx *c, const double *f_new_dev, const double *f_old_dev, 
 tr_status tr_step(tr_ctx *c, const double *n_h_dev, const double *f_prev_dev, double *f_out_dev,
                   uint8_t *ionised_out_dev, double *delta_host);
 
-/* Outer iteration (Sec. 2.5): an optically thin build+sweep, then build+sweep
+/* Outer iteration (Sec. 2.6): an optically thin build+sweep, then build+sweep
  * with the last flux until every domain has delta_cell < eps_lim or max_iter
  * sweeps.  f_out_dev receives the last flux, iters_out the absorbing sweeps,
  * delta_out the largest delta of the last one.  Returns TR_ENOCONV if the

@@ -111,7 +111,7 @@ int orc_cell_geometry(const orc_domain *d, int64_t *lo3, int64_t *size)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Sources onto the grid (Sec. 2.1 "Mapping sources onto the grid", Sec. 2.6)
+/* Sources onto the grid (Sec. 2.1 "Mapping sources onto the grid", Sec. 2.7)
  * reading: point sources, i.e. the limit of a vanishing source radius: the
  * rate is split equally over every leaf cell whose closed extent contains
  * the point.  A coordinate within 1e-9 finest cells of a cell face is taken
@@ -936,7 +936,7 @@ int64_t orc_accepted(const orc_domain *d, const orc_params *p, const double *n_h
 }
 
 /* ------------------------------------------------------------------------ */
-/* Error control (Sec. 2.5 "Iterations and error control")
+/* Error control (Sec. 2.6 "Iterations and error control")
  * delta_cell = max_c |F_new - F_old| / max(F_old, median F_old) (eq.
  * delta:er:cell with its normaliser); reading: the change is taken in
  * absolute value, the median is the lower median over all cells, and a cell

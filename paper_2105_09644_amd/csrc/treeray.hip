@@ -1,7 +1,7 @@
 // TreeRay/OnTheSpot on MI355X (gfx950): device kernels and the C ABI.
 //
 // Steps of one outer iteration (paper Sec. 2):
-//   k_fill / k_deposit     point sources onto the leaf cells (Sec. 2.1, 2.6)
+//   k_fill / k_deposit     point sources onto the leaf cells (Sec. 2.1, 2.7)
 //   k_cell_quantities      eps, alpha, e of every cell (eqs. os:ems, os:abs, os:erd)
 //   k_reduce_level         FP64 bottom-up node moments, one launch per tree level
 //   k_pack                 node records for the sweep (FP64 or FP32, SoA)

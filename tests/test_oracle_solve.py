@@ -1,4 +1,4 @@
-"""Pins of the oracle's error control and outer iteration (paper Sec. 2.5)."""
+"""Pins of the oracle's error control and outer iteration (paper Sec. 2.6)."""
 import math
 
 import numpy as np
@@ -32,7 +32,7 @@ def test_delta_tot(orc):
 def test_stromgren_trend_with_opening_angle(orc):
     # Uniform gas around one source (16^3, Q = 1e48, n_H = 100): the converged
     # ionised volume approaches the Stromgren sphere as the opening angle
-    # shrinks (the paper's convergence claim, Sec. 5).  The front recedes
+    # shrinks (the convergence claim of the paper, Sec. 6).  The front recedes
     # monotonically from the optically thin start: a cell once dark keeps
     # zeta_d = 2, so it is not re-ionised.
     P = W.small_uniform(16)

@@ -1,5 +1,5 @@
 """Pins of the oracle's source deposit, octree, node moments and tree walk
-(paper Sec. 2.1, 2.3, 2.4, 2.6).
+(paper Sec. 2.1, 2.3, 2.4, 2.7).
 
 Independent references are built here in numpy from the inputs alone: cell
 centres of a uniform grid, painted occupancy grids, brute-force sums over all
