@@ -118,37 +118,51 @@ int orc_cell_geometry(const orc_domain *d, int64_t *lo3, int64_t *size)
  * to lie on it.                                                             */
 /* ------------------------------------------------------------------------ */
 
+static int cell_contains(const grid_t *g, int64_t c, const double u[3])
+{
+    const int64_t *lo = g->lo + 3 * c;
+    double sz = (double)g->size[c];
+    return u[0] >= lo[0] && u[0] <= lo[0] + sz && u[1] >= lo[1] && u[1] <= lo[1] + sz &&
+           u[2] >= lo[2] && u[2] <= lo[2] + sz;
+}
+
 static int deposit(const grid_t *g, int64_t n_src, const double *xyz, const double *q,
                    double *ndot)
 {
-    memset(ndot, 0, sizeof(double) * (size_t)g->n);
+    /* the cells holding each source are found independently per source (a
+     * point of a tiling lies in at most 8 closed cells); the rates are then
+     * added in source order */
+    int64_t *hit = (int64_t *)malloc(sizeof(int64_t) * 9 * (size_t)(n_src > 0 ? n_src : 1));
+    if (!hit) return -2;
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
     for (int64_t s = 0; s < n_src; ++s) {
+        int64_t *h = hit + 9 * s;
+        h[0] = 0;
         double u[3];
         for (int a = 0; a < 3; ++a) {
             u[a] = xyz[3 * s + a] / g->dx;
             double rn = floor(u[a] + 0.5);
             if (fabs(u[a] - rn) <= 1e-9) u[a] = rn;
-            if (u[a] < 0 || u[a] > (double)g->ext[a]) return -1;
+            if (u[a] < 0 || u[a] > (double)g->ext[a]) bad = 1;
         }
-        if (!(q[s] >= 0) || !isfinite(q[s])) return -1;
-        int64_t count = 0;
-        for (int64_t c = 0; c < g->n; ++c) {
-            const int64_t *lo = g->lo + 3 * c;
-            double sz = (double)g->size[c];
-            if (u[0] >= lo[0] && u[0] <= lo[0] + sz && u[1] >= lo[1] && u[1] <= lo[1] + sz &&
-                u[2] >= lo[2] && u[2] <= lo[2] + sz)
-                ++count;
-        }
-        if (count == 0) return -1;
-        for (int64_t c = 0; c < g->n; ++c) {
-            const int64_t *lo = g->lo + 3 * c;
-            double sz = (double)g->size[c];
-            if (u[0] >= lo[0] && u[0] <= lo[0] + sz && u[1] >= lo[1] && u[1] <= lo[1] + sz &&
-                u[2] >= lo[2] && u[2] <= lo[2] + sz)
-                ndot[c] += q[s] / (double)count;
-        }
+        if (!(q[s] >= 0) || !isfinite(q[s])) bad = 1;
+        if (bad) continue;
+        for (int64_t c = 0; c < g->n; ++c)
+            if (cell_contains(g, c, u)) {
+                if (h[0] == 8) { bad = 1; break; }
+                h[1 + h[0]++] = c;
+            }
+        if (h[0] == 0) bad = 1;
     }
-    return 0;
+    memset(ndot, 0, sizeof(double) * (size_t)g->n);
+    if (!bad)
+        for (int64_t s = 0; s < n_src; ++s) {
+            const int64_t *h = hit + 9 * s;
+            for (int64_t m = 0; m < h[0]; ++m) ndot[h[1 + m]] += q[s] / (double)h[0];
+        }
+    free(hit);
+    return bad ? -1 : 0;
 }
 
 int orc_deposit(const orc_domain *d, int64_t n_src, const double *src_xyz_cm,

@@ -209,6 +209,7 @@ struct SweepArgs {
     double theta2;
     float guard_tol;
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
+    int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
 };
 
 // ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
@@ -221,6 +222,16 @@ __device__ inline void buf_add(Real *p, Real v)
         __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
         *p += v;
+}
+
+// outermost emitting point of a ray
+template <bool ATOMIC>
+__device__ inline void top_max(int *p, int v)
+{
+    if constexpr (ATOMIC)
+        __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        *p = *p > v ? *p : v;
 }
 
 // Phi (photon rate per steradian) lives in the eps slot of a point once the
@@ -250,7 +261,9 @@ __device__ inline double drcp(double x)
     return fma(r, e, r);
 }
 
-// One ray (Sec. 2.5): march inwards from the last point, all sources together.
+// One ray (Sec. 2.5), one lane: march inwards from the outermost point that
+// holds emission (top; nothing reaches the target from beyond it), all
+// sources together.
 // Per segment [r_i, r_{i+1}] and source j beyond it:
 //   R = (alpha_i + alpha_{i+1})/2 dV_{i,j} zeta_s zeta_d zeta_g,
 //   zeta_s zeta_d = F_{i+1,j} min(2/F_{i+1}, 1/Fbar_{i+1})   (zeta_d = 2 where Fbar = 0),
@@ -258,14 +271,14 @@ __device__ inline double drcp(double x)
 // and the source at r_{i+1} itself takes zeta_s = zeta_d = 1.
 // Returns F_{0,k} in internal flux units.
 template <typename Real>
-__device__ double integrate_ray(Real *b, int kbase, const double *r, const double *inv2r, int nr, int nrm, int nside,
-                                int zeta_g)
+__device__ double integrate_ray(Real *b, int kbase, const double *r, const double *inv2r, int nr, int nrm, int top,
+                                int nside, int zeta_g)
 {
     const double inv4pi = 1.0 / (4.0 * kPi);
     const double ns = (double)nside;
     uint64_t m0 = 0, m1 = 0;     // points j holding a live Phi_j
     double a1 = 0.0, fb1 = 0.0;  // alpha and previous flux at r_{i+1}
-    for (int i = nr - 1; i >= 0; --i) {
+    for (int i = top; i >= 0; --i) {
         const double Vi = (double)b[kbase + Q_V * nrm + i];
         double ai = 0.0, fbi = 0.0;
         if (Vi > 0.0) {
@@ -336,6 +349,91 @@ __device__ double integrate_ray(Real *b, int kbase, const double *r, const doubl
     return f0;
 }
 
+template <typename T>
+__device__ inline T rdlane(T v, int l);
+
+// value of point i held by lane i % 64 of the pair (v[0], v[1]); i uniform
+__device__ inline double point_value(const double v[2], int i)
+{
+    return i < 64 ? rdlane(v[0], i) : rdlane(v[1], i - 64);
+}
+
+// The same march with a whole wave on one ray: lane p holds point p (and
+// p + 64), so every source on the ray advances in the same step and the
+// total flux F_{i+1} is a wave reduction.  Phi stays in registers.  Returns
+// F_{0,k} (uniform) in internal flux units.
+template <typename Real>
+__device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, const double *inv2r, int nr, int nrm,
+                                     int top, int nside, int zeta_g)
+{
+    const int lane = lane_id();
+    const double inv4pi = 1.0 / (4.0 * kPi);
+    const double ns = (double)nside;
+    double al[2], fb[2], ph[2], rp[2], i2r[2], ep[2];
+    bool live[2];
+    for (int h = 0; h < 2; ++h) {
+        const int p = lane + 64 * h;
+        al[h] = fb[h] = ph[h] = ep[h] = rp[h] = i2r[h] = 0.0;
+        live[h] = false;
+        if (p < nr) {
+            const double V = (double)b[kbase + Q_V * nrm + p];
+            if (V > 0.0) {
+                const double rv = drcp(V);
+                al[h] = (double)b[kbase + Q_A * nrm + p] * rv;
+                fb[h] = (double)b[kbase + Q_E * nrm + p] * rv;
+            }
+            ep[h] = (double)b[kbase + Q_EPS * nrm + p];
+            rp[h] = r[p];
+            i2r[h] = inv2r[p];
+        }
+    }
+    bool any = false;   // uniform: some source on the ray is still live
+    for (int i = top; i >= 0; --i) {
+        if (i <= nr - 2 && any) {
+            const double ri = r[i], ri1 = r[i + 1];
+            const double ai = point_value(al, i), ai1 = point_value(al, i + 1), fb1 = point_value(fb, i + 1);
+            double f[2], fs = 0.0;
+            for (int h = 0; h < 2; ++h) {
+                f[h] = 0.0;
+                if (live[h] && lane + 64 * h >= i + 2) {
+                    const double B = rp[h] - ri1;
+                    f[h] = ph[h] * drcp(B * B);
+                }
+                fs += f[h];
+            }
+            const double ftot = wave_sum(fs);
+            double g = 0.0;
+            if (ftot > 0.0) {
+                g = 2.0 * drcp(ftot);
+                if (fb1 > 0.0) g = fmin(g, drcp(fb1));
+            }
+            const double aseg = 0.5 * (ai + ai1) * (ri1 - ri) * (1.0 / 3.0);
+            for (int h = 0; h < 2; ++h) {
+                if (live[h]) {
+                    const double A = rp[h] - ri, B = rp[h] - ri1;
+                    double z = lane + 64 * h >= i + 2 ? f[h] * g : 1.0;
+                    if (zeta_g) z *= fmin(1.0, ns * A * i2r[h]);
+                    ph[h] = fmax(0.0, ph[h] - aseg * (A * A + A * B + B * B) * z);
+                    live[h] = ph[h] > 0.0;
+                }
+            }
+            any = __ballot(live[0] || live[1]) != 0ull;
+        }
+        if (i >= 1 && point_value(ep, i) > 0.0) {
+            const int h = i >> 6;
+            if (lane == (i & 63)) {
+                ph[h] = ep[h] * inv4pi;
+                live[h] = true;
+            }
+            any = true;
+        }
+    }
+    double s = 0.0;
+    for (int h = 0; h < 2; ++h)
+        if (live[h]) s += ph[h] * drcp(rp[h] * rp[h]);
+    return wave_sum(s);
+}
+
 // c_magic[n] = ceil(2^16 / n): (l * c_magic[n]) >> 16 == l / n for 0 <= l < 64, 1 <= n <= 64
 __constant__ uint32_t c_magic[65] = {
     0, 65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554, 5958, 5462, 5042, 4682, 4370, 4096,
@@ -367,7 +465,7 @@ __device__ inline T rdlane(T v, int l)
 // The evaluation points are r_i = c i^2; the per-node loop recomputes them
 // in registers, so it makes no memory round trip besides its atomics.
 template <typename Real, bool ATOMIC>
-__device__ void map_nodes(const SweepArgs &a, Real *buf, const Real *rt, int nr, Real rc_inv, Real rcoef,
+__device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *rt, int nr, Real rc_inv, Real rcoef,
                           const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
 {
     using R4 = typename R4T<Real>::T;
@@ -497,27 +595,45 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, const Real *rt, int nr,
             wv = w * jv;
         }
         const int col = Q_A * nrm + jlo + io;
-        // --- distinct pixels; scattered in batches of G ---
+        // --- distinct pixels: slot q (lane q of slot_k / slot_c) holds pixel k_q and its count ---
         uint64_t rem = act_mask;
-        int q = 0, myk = -1;
-        Real myw = 0;
+        int nd = 0, slot_k = 0, slot_c = 0;
         while (rem) {
             const int first = __ffsll((unsigned long long)rem) - 1;
             const int k = __builtin_amdgcn_readlane(pix, first);
             const uint64_t m = __ballot(pix == k) & rem;
             rem &= ~m;
-            const Real wk = (Real)__popcll(m) * inv_s3;
-            if (po == q) {
-                myk = k;
-                myw = wk;
+            if (lane == nd) {
+                slot_k = k;
+                slot_c = (int)__popcll(m);
             }
-            if (has_eps && lane < 2) {
-                const Real ev = lane == 0 ? je0 : je1;
-                if (ev != (Real)0)
-                    buf_add<Real, ATOMIC>(buf + (size_t)k * a.stride_k + Q_EPS * nrm + jie + lane, wk * ev);
+            ++nd;
+        }
+        // emission: lane q deposits pixel q's share on the two bracket points
+        if (has_eps && lane < nd) {
+            const Real wk = (Real)slot_c * inv_s3;
+            Real *row = buf + (size_t)slot_k * a.stride_k + Q_EPS * nrm + jie;
+            if (je0 != (Real)0) buf_add<Real, ATOMIC>(row, wk * je0);
+            if (je1 != (Real)0) buf_add<Real, ATOMIC>(row + 1, wk * je1);
+            top_max<ATOMIC>(top + slot_k, je1 != (Real)0 ? jie + 1 : jie);
+        }
+        // A, E, V: lanes cover (pixel slot, point) pairs, G slots at a time
+        for (int b0 = 0; b0 < nd; b0 += G) {
+            const int q = b0 + po;
+            const int kq = __shfl(slot_k, q & 63, 64), cq = __shfl(slot_c, q & 63, 64);
+            if (lane_ok && q < nd) {
+                const Real wk = (Real)cq * inv_s3;
+                Real *row = buf + (size_t)kq * a.stride_k + col;
+                buf_add<Real, ATOMIC>(row, wk * wa);
+                buf_add<Real, ATOMIC>(row + nrm, wk * we);
+                buf_add<Real, ATOMIC>(row + 2 * nrm, wk * wv);
             }
-            if (jn > 64) {
-                // support wider than a wave (N_R > 64): the remaining points of this pixel
+        }
+        if (jn > 64) {
+            // support wider than a wave (N_R > 64): the remaining points, pixel by pixel
+            for (int q = 0; q < nd; ++q) {
+                const int k = __builtin_amdgcn_readlane(slot_k, q);
+                const Real wk = (Real)__builtin_amdgcn_readlane(slot_c, q) * inv_s3;
                 Real *row = buf + (size_t)k * a.stride_k + Q_A * nrm + jlo;
                 for (int i2 = 64 + lane; i2 < jn; i2 += 64) {
                     const int i = jlo + i2;
@@ -526,17 +642,6 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, const Real *rt, int nr,
                     buf_add<Real, ATOMIC>(row + nrm + i2, wk * w2 * je);
                     buf_add<Real, ATOMIC>(row + 2 * nrm + i2, wk * w2 * jv);
                 }
-            }
-            ++q;
-            if (q == G || rem == 0) {
-                if (lane_ok && myk >= 0) {
-                    Real *row = buf + (size_t)myk * a.stride_k + col;
-                    buf_add<Real, ATOMIC>(row, myw * wa);
-                    buf_add<Real, ATOMIC>(row + nrm, myw * we);
-                    buf_add<Real, ATOMIC>(row + 2 * nrm, myw * wv);
-                }
-                q = 0;
-                myk = -1;
             }
         }
     }
@@ -656,6 +761,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
     int *sc = (int *)p;
     p += S_COUNT * sizeof(int);
     double *red = (double *)p;
+    p += WAVES * sizeof(double);
+    int *top = (int *)p;   // per ray: outermost point holding emission (0: none)
 
     double n_acc = 0, n_test = 0, n_guard = 0;
 
@@ -723,6 +830,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
                 for (int i = lane; i < nr; i += 64)
                     dst[i] = row == Q_EPS ? (Real)0 : mom * (wself[i] * inv_npix);
             }
+            for (int k = tid; k < npix; k += WAVES * 64) top[k] = 0;
         }
         __syncthreads();
 
@@ -748,7 +856,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
             }
             end = uniform(end);
             if (end <= start) break;
-            map_nodes<Real, ATOMIC>(a, buf, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz, n_guard);
+            map_nodes<Real, ATOMIC>(a, buf, top, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz, n_guard);
         }
         __syncthreads();
         if (sc[S_OVF]) {
@@ -762,11 +870,33 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
         }
         n_acc += (wave == 0 && lane == 0) ? (double)sc[S_TOTAL] : 0.0;
 
-        // --- per-ray integration and the sum over rays ---
-        // rays spread over all waves: ray k on wave k % WAVES
+        // --- per-ray integration and the sum over rays (rays without emission give 0) ---
         double fsum = 0.0;
-        for (int k = lane * WAVES + wave; k < npix; k += 64 * WAVES)
-            fsum += integrate_ray<Real>(buf, k * a.stride_k, rd, rd2, nr, nrm, a.nside, a.zeta_g);
+        if (a.int_wave) {
+            // a wave per ray, the emitting rays dealt round robin over the waves
+            int seen = 0;
+            for (int base = 0; base < npix; base += 64) {
+                const int t = base + lane < npix ? top[base + lane] : 0;
+                uint64_t m = __ballot(t > 0);
+                while (m) {
+                    const int l = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    if (seen % WAVES == wave) {
+                        const int tk = __builtin_amdgcn_readlane(t, l);
+                        const double f = integrate_ray_wave<Real>(buf, (base + l) * a.stride_k, rd, rd2, nr, nrm, tk,
+                                                                  a.nside, a.zeta_g);
+                        if (lane == 0) fsum += f;
+                    }
+                    ++seen;
+                }
+            }
+        } else {
+            // a lane per ray: ray k on lane k % 64 of wave (k / 64) % WAVES
+            for (int k = wave * 64 + lane; k < npix; k += 64 * WAVES) {
+                const int t = top[k];
+                if (t > 0) fsum += integrate_ray<Real>(buf, k * a.stride_k, rd, rd2, nr, nrm, t, a.nside, a.zeta_g);
+            }
+        }
         fsum = wave_sum(fsum);
         if (lane == 0) red[wave] = fsum;
         __syncthreads();
@@ -943,10 +1073,11 @@ struct tr_ctx {
     // state
     bool built = false;
     tr_precision built_prec = TR_FP64;
-    int32_t waves = 0, tpc = 0, bufmode = 0;   // user launch shape (0 = default)
-    int32_t last_waves = 0, last_tpc = 0, last_lds = 0;
+    int32_t waves = 0, tpc = 0, bufmode = 0, intmode = 0;   // user launch shape (0 = default)
+    int32_t last_waves = 0, last_tpc = 0, last_lds = 0, last_intw = 0;
     int tuned_waves[2] = {0, 0};         // per precision after tr_autotune
     int tuned_buf[2] = {0, 0};
+    int tuned_int[2] = {0, 0};
     float last_ms = 0.f;
     bool timed_valid = false;            // ev0/ev1 bracket a recorded sweep
     // one outer iteration captured as a hipGraph (tr_step)
@@ -1056,6 +1187,7 @@ size_t sweep_lds_bytes(size_t real, int npix, int stride_k, int nrm, int fmax, i
     b += 2 * (size_t)fmax * 4 + (size_t)amax * 4;
     b += 16 * 4;
     b += (size_t)waves * 8;
+    b += (size_t)npix * 4;
     return b;
 }
 
@@ -1086,9 +1218,10 @@ struct LaunchPlan {
     int waves = 0, blocks = 0, per_cu = 0, fmax = 0, amax = 0, stride_k = 0;
     size_t lds = 0;
     bool ldsbuf = true;
+    bool intw = false;   // a wave per ray in the integration
 };
 
-tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int buf_req, LaunchPlan &L)
+tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int buf_req, int int_req, LaunchPlan &L)
 {
     const bool f32 = c->p.precision == TR_FP32C;
     const size_t real = f32 ? 4 : 8;
@@ -1120,6 +1253,10 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)L.fn, waves * 64, L.lds));
     if (occ <= 0) return fail(c, TR_EINVAL, "sweep kernel does not fit on a compute unit (LDS " + std::to_string(L.lds) + " B)");
     L.per_cu = tpc_req > 0 ? std::min(tpc_req, occ) : occ;
+    // integration: a wave per ray hides the march's latency when few targets
+    // share a compute unit; a lane per ray issues fewer instructions otherwise
+    int im = int_req > 0 ? int_req : c->tuned_int[f32 ? 1 : 0];
+    L.intw = im > 0 ? im == 2 : L.per_cu <= 2;
     int64_t blocks = (int64_t)c->n_cu * L.per_cu;
     if (blocks > n_items) blocks = std::max<int64_t>(1, n_items);
     L.blocks = (int)blocks;
@@ -1136,14 +1273,14 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
 }
 
 tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_out, uint8_t *ion, bool timed,
-                       int waves_req, int tpc_req, int buf_req)
+                       int waves_req, int tpc_req, int buf_req, int int_req)
 {
     if (!c->built) return fail(c, TR_ESTATE, "tr_sweep needs tr_build first");
     if (c->built_prec != c->p.precision) return fail(c, TR_ESTATE, "precision changed since tr_build; build again");
     if (n == 0) return TR_OK;
     LaunchPlan L;
     tr_status s = plan_sweep(c, n, waves_req > 0 ? waves_req : c->waves, tpc_req > 0 ? tpc_req : c->tpc,
-                             buf_req > 0 ? buf_req : c->bufmode, L);
+                             buf_req > 0 ? buf_req : c->bufmode, int_req > 0 ? int_req : c->intmode, L);
     if (s) return s;
     SweepArgs a{};
     a.geo = c->geo;
@@ -1178,6 +1315,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.nr_max = c->nr_max;
     a.stride_k = L.stride_k;
     a.zeta_g = c->p.zeta_g;
+    a.int_wave = L.intw ? 1 : 0;
     (void)hipGetLastError();   // a stale error of an earlier, unrelated call is not ours
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->queue, (int64_t)2, 0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, c->stats, (int64_t)4);
@@ -1191,6 +1329,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     c->last_waves = L.waves;
     c->last_tpc = L.per_cu;
     c->last_lds = L.ldsbuf ? 1 : 0;
+    c->last_intw = L.intw ? 1 : 0;
     return TR_OK;
 }
 
@@ -1530,14 +1669,14 @@ tr_status tr_sweep(tr_ctx *c, double *f_out, uint8_t *ion)
 {
     if (!c) return TR_EINVAL;
     if (!f_out) return fail(c, TR_EINVAL, "f_out is NULL");
-    return launch_sweep(c, nullptr, c->n_cells, f_out, ion, true, 0, 0, 0);
+    return launch_sweep(c, nullptr, c->n_cells, f_out, ion, true, 0, 0, 0, 0);
 }
 
 tr_status tr_sweep_targets(tr_ctx *c, const int64_t *targets, int64_t n, double *f_out, uint8_t *ion)
 {
     if (!c) return TR_EINVAL;
     if (n < 0 || (n > 0 && (!targets || !f_out))) return fail(c, TR_EINVAL, "bad target list");
-    return launch_sweep(c, targets, n, f_out, ion, true, 0, 0, 0);
+    return launch_sweep(c, targets, n, f_out, ion, true, 0, 0, 0, 0);
 }
 
 tr_status tr_delta(tr_ctx *c, const double *f_new, const double *f_old, double *delta_host)
@@ -1577,7 +1716,7 @@ tr_status tr_step(tr_ctx *c, const double *n_h, const double *f_prev, double *f_
         drop_slot(*slot);
         // plan (and allocate) the sweep before capturing it
         LaunchPlan L;
-        if ((s = plan_sweep(c, c->n_cells, c->waves, c->tpc, c->bufmode, L))) return s;
+        if ((s = plan_sweep(c, c->n_cells, c->waves, c->tpc, c->bufmode, c->intmode, L))) return s;
         if (!c->cap_stream) HIPCHK(hipStreamCreate(&c->cap_stream));
         if (!c->pinned) HIPCHK(hipHostMalloc(&c->pinned, 64 + sizeof(unsigned long long) * (size_t)nd));
         hipStream_t user = c->stream;
@@ -1588,7 +1727,7 @@ tr_status tr_step(tr_ctx *c, const double *n_h, const double *f_prev, double *f_
         const tr_precision bp = c->built_prec;
         c->built = true;
         c->built_prec = c->p.precision;
-        if (!cs) cs = launch_sweep(c, nullptr, c->n_cells, f_out, ion, false, 0, 0, 0);
+        if (!cs) cs = launch_sweep(c, nullptr, c->n_cells, f_out, ion, false, 0, 0, 0, 0);
         c->built = built;
         c->built_prec = bp;
         if (!cs) cs = enqueue_delta(c, f_out, f_prev);
@@ -1676,16 +1815,19 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec)
     return TR_OK;
 }
 
-tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer)
+tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer, int32_t integration)
 {
     if (!c) return TR_EINVAL;
     if (buffer < 0 || buffer > 2) return fail(c, TR_EINVAL, "buffer must be 0 (auto), 1 (LDS) or 2 (device memory)");
+    if (integration < 0 || integration > 2)
+        return fail(c, TR_EINVAL, "integration must be 0 (auto), 1 (a lane per ray) or 2 (a wave per ray)");
     if (!(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16))
         return fail(c, TR_EINVAL, "waves per target must be 0, 1, 2, 4, 8 or 16");
     if (tpc < 0) return fail(c, TR_EINVAL, "targets per CU must be >= 0");
     c->waves = waves;
     c->tpc = tpc;
     c->bufmode = buffer;
+    c->intmode = integration;
     drop_graph(c);
     return TR_OK;
 }
@@ -1710,25 +1852,30 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
     HIPCHK(hipMemcpyAsync(dt, tg.data(), sizeof(int64_t) * tg.size(), hipMemcpyHostToDevice, c->stream));
     const int cand[5] = {1, 2, 4, 8, 16};
     double best = INFINITY;
-    int bw = 0, bb = 0;
+    int bw = 0, bb = 0, bi = 0;
     for (int bm = 1; bm <= 2; ++bm)
-        for (int w : cand) {
-            LaunchPlan L;
-            if (plan_sweep(c, (int64_t)tg.size(), w, 0, bm, L) != TR_OK) continue;
-            float ms = 0, tot = 0;
-            bool ok = true;
-            for (int rep = 0; rep < 3 && ok; ++rep) {
-                if (launch_sweep(c, dt, (int64_t)tg.size(), fo, nullptr, true, w, 0, bm) != TR_OK) { ok = false; break; }
-                if (hipEventSynchronize(c->ev1) != hipSuccess) { ok = false; break; }
-                (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
-                if (rep > 0) tot += ms;
+        for (int w : cand)
+            for (int im = 1; im <= 2; ++im) {
+                LaunchPlan L;
+                if (plan_sweep(c, (int64_t)tg.size(), w, 0, bm, im, L) != TR_OK) continue;
+                float ms = 0, tot = 0;
+                bool ok = true;
+                for (int rep = 0; rep < 3 && ok; ++rep) {
+                    if (launch_sweep(c, dt, (int64_t)tg.size(), fo, nullptr, true, w, 0, bm, im) != TR_OK) {
+                        ok = false;
+                        break;
+                    }
+                    if (hipEventSynchronize(c->ev1) != hipSuccess) { ok = false; break; }
+                    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+                    if (rep > 0) tot += ms;
+                }
+                if (ok && tot / 2 < best) {
+                    best = tot / 2;
+                    bw = w;
+                    bb = bm;
+                    bi = im;
+                }
             }
-            if (ok && tot / 2 < best) {
-                best = tot / 2;
-                bw = w;
-                bb = bm;
-            }
-        }
     dfree(dt);
     dfree(fo);
     c->err.clear();
@@ -1736,6 +1883,7 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
     if (bw == 0) return fail(c, TR_EHIP, "no launch shape ran");
     c->tuned_waves[c->p.precision == TR_FP32C ? 1 : 0] = bw;
     c->tuned_buf[c->p.precision == TR_FP32C ? 1 : 0] = bb;
+    c->tuned_int[c->p.precision == TR_FP32C ? 1 : 0] = bi;
     drop_graph(c);
     if (best_ms) *best_ms = best;
     return TR_OK;
@@ -1760,6 +1908,7 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
     out->waves_per_target = c->last_waves;
     out->targets_per_cu = c->last_tpc;
     out->buffer_in_lds = c->last_lds;
+    out->integration_wave = c->last_intw;
     out->overflow = q[1];
     float ms = 0;
     if (c->timed_valid && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) out->last_sweep_ms = ms;

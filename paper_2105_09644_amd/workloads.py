@@ -290,4 +290,21 @@ def small_amr(nroot: int = 2, seed: int = 0, threshold: float = 150.0,
     return Problem(f"amr{nroot}_{seed}", [dom], [nh], [xyz], [q], p)
 
 
+def prev_flux_field(problem: Problem, seed: int = 0, dark_fraction: float = 0.2,
+                    sigma: float = 1.0) -> np.ndarray:
+    """Synthetic previous-iteration flux for every cell of ``problem``, an input
+    that both sides of a parity test take: log-normal values (sigma in ln) on
+    the scale of the total source rate spread over a sphere of a quarter of
+    the first domain's side, with a random ``dark_fraction`` of cells at zero.
+    Photons cm^-2 s^-1, float64, domains concatenated."""
+    rng = rng_for(96, seed)
+    n = problem.total_cells()
+    side = problem.domains[0].root_block_cm * problem.domains[0].nroot[0]
+    qtot = sum(float(np.sum(q)) for q in problem.src_q)
+    scale = qtot / (4.0 * np.pi * (0.25 * side) ** 2)
+    f = scale * np.exp(sigma * rng.standard_normal(n))
+    f[rng.random(n) < dark_fraction] = 0.0
+    return f
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
