@@ -278,15 +278,23 @@ __device__ double integrate_ray(Real *b, int kbase, const double *r, const doubl
     const double ns = (double)nside;
     uint64_t m0 = 0, m1 = 0;     // points j holding a live Phi_j
     double a1 = 0.0, fb1 = 0.0;  // alpha and previous flux at r_{i+1}
+    // the point's buffer entries are fetched one step ahead
+    Real nV = b[kbase + Q_V * nrm + top], nA = b[kbase + Q_A * nrm + top], nE = b[kbase + Q_E * nrm + top],
+         nEps = b[kbase + Q_EPS * nrm + top];
     for (int i = top; i >= 0; --i) {
-        const double Vi = (double)b[kbase + Q_V * nrm + i];
+        const double Vi = (double)nV, Ai = (double)nA, Ei = (double)nE, ei = (double)nEps;
+        if (i > 0) {
+            nV = b[kbase + Q_V * nrm + i - 1];
+            nA = b[kbase + Q_A * nrm + i - 1];
+            nE = b[kbase + Q_E * nrm + i - 1];
+            nEps = b[kbase + Q_EPS * nrm + i - 1];
+        }
         double ai = 0.0, fbi = 0.0;
         if (Vi > 0.0) {
             const double rv = drcp(Vi);
-            ai = (double)b[kbase + Q_A * nrm + i] * rv;
-            fbi = (double)b[kbase + Q_E * nrm + i] * rv;
+            ai = Ai * rv;
+            fbi = Ei * rv;
         }
-        const double ei = (double)b[kbase + Q_EPS * nrm + i];
         if (i <= nr - 2 && (m0 | m1)) {
             const double ri = r[i], ri1 = r[i + 1], seg = ri1 - ri;
             // F_{i+1}: flux at r_{i+1} from the sources beyond it
@@ -546,34 +554,40 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
     const float inv_s = 1.0f / (float)s;
     const Real inv_s3 = (Real)1 / (Real)s3;
     const uint64_t act_mask = __ballot(active);
+    const int packed = lo | (nsup << 8) | (ie << 16);   // each below 256
+    // per node (lane = node): sub-box origin relative to the target and sub-box steps, FP32
+    const float ox = 0.5f * (float)(2 * bx - tx), oy = 0.5f * (float)(2 * by - ty), oz = 0.5f * (float)(2 * bz - tz);
+    const float sx = (float)ex * inv_s, sy = (float)ey * inv_s, sz = (float)ez * inv_s;
     for (int j = 0; j < cnt; ++j) {
-        const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
-        const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
         // --- angular ---
         int pix = 0;
         if constexpr (sizeof(Real) == 4) {
-            const float vx = fmaf(ca, (float)jex * inv_s, 0.5f * (float)(2 * jbx - tx));
-            const float vy = fmaf(cb, (float)jey * inv_s, 0.5f * (float)(2 * jby - ty));
-            const float vz = fmaf(cc, (float)jez * inv_s, 0.5f * (float)(2 * jbz - tz));
+            const float vx = fmaf(ca, rdlane(sx, j), rdlane(ox, j));
+            const float vy = fmaf(cb, rdlane(sy, j), rdlane(oy, j));
+            const float vz = fmaf(cc, rdlane(sz, j), rdlane(oz, j));
             bool unsure = false;
             pix = ang2pix_f(ns, vx, vy, vz, a.guard_tol, unsure);
             unsure &= active;
             if (__ballot(unsure)) {
+                const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
+                const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
                 if (unsure) {
                     pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
                     guard_count += 1.0;
                 }
             }
         } else {
+            const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
+            const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
             if (active) pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
         }
         pix = pix < 0 ? 0 : (pix >= a.npix ? a.npix - 1 : pix);
         // --- radial weights: this lane serves support point lo + io of batch slot po ---
-        const int jlo = rdlane(lo, j), jn = rdlane(nsup, j);
+        const int jpk = rdlane(packed, j);
+        const int jlo = jpk & 255, jn = (jpk >> 8) & 255, jie = jpk >> 16;
         const Real jd = rdlane(d, j), jhinv = rdlane(hinv, j), jws = rdlane(wscale, j), jfb = rdlane(fb0, j);
         const Real ja = rdlane(qa, j), je = rdlane(qe, j), jv = rdlane(qv, j);
         const Real je0 = rdlane(e0, j), je1 = rdlane(e1, j);
-        const int jie = rdlane(ie, j);
         const bool has_eps = je0 != (Real)0 || je1 != (Real)0;
         const int span = jn < 64 ? jn : 64;                         // points per batch slot
         const int G = 64 / span;                                    // pixels per batch
@@ -726,7 +740,7 @@ __device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz
 }
 
 template <typename Real, int WAVES, bool LDSBUF>
-__global__ __launch_bounds__(WAVES * 64) void k_sweep(SweepArgs a)
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
 {
     using R4 = typename R4T<Real>::T;
     constexpr bool ATOMIC = WAVES > 1;
