@@ -370,7 +370,7 @@ __device__ inline double point_value(const double v[2], int i)
 // p + 64), so every source on the ray advances in the same step and the
 // total flux F_{i+1} is a wave reduction.  Phi stays in registers.  Returns
 // F_{0,k} (uniform) in internal flux units.
-template <typename Real>
+template <typename Real, int NH>
 __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, const double *inv2r, int nr, int nrm,
                                      int top, int nside, int zeta_g)
 {
@@ -379,6 +379,7 @@ __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, 
     const double ns = (double)nside;
     double al[2], fb[2], ph[2], rp[2], i2r[2], ep[2];
     bool live[2];
+#pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int p = lane + 64 * h;
         al[h] = fb[h] = ph[h] = ep[h] = rp[h] = i2r[h] = 0.0;
@@ -401,7 +402,9 @@ __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, 
             const double ri = r[i], ri1 = r[i + 1];
             const double ai = point_value(al, i), ai1 = point_value(al, i + 1), fb1 = point_value(fb, i + 1);
             double f[2], fs = 0.0;
-            for (int h = 0; h < 2; ++h) {
+            f[1] = 0.0;
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
                 f[h] = 0.0;
                 if (live[h] && lane + 64 * h >= i + 2) {
                     const double B = rp[h] - ri1;
@@ -416,7 +419,8 @@ __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, 
                 if (fb1 > 0.0) g = fmin(g, drcp(fb1));
             }
             const double aseg = 0.5 * (ai + ai1) * (ri1 - ri) * (1.0 / 3.0);
-            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
                 if (live[h]) {
                     const double A = rp[h] - ri, B = rp[h] - ri1;
                     double z = lane + 64 * h >= i + 2 ? f[h] * g : 1.0;
@@ -437,7 +441,8 @@ __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, 
         }
     }
     double s = 0.0;
-    for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
         if (live[h]) s += ph[h] * drcp(rp[h] * rp[h]);
     return wave_sum(s);
 }
@@ -835,14 +840,26 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         __syncthreads();
         // ray buffer: zero emission, the target's own share of A, E, V
         {
+            // every ray starts from the same 4 N_R values: lane l holds entries l + 64 m
             const Real inv_npix = (Real)1 / (Real)npix;
-            const size_t rows = (size_t)npix * 4;
-            for (size_t q = wave; q < rows; q += WAVES) {
-                const int k = (int)(q >> 2), row = (int)(q & 3);
-                Real *dst = buf + (size_t)k * a.stride_k + row * nrm;
-                const Real mom = row == Q_A ? tB.x : row == Q_E ? tB.y : tB.z;
-                for (int i = lane; i < nr; i += 64)
-                    dst[i] = row == Q_EPS ? (Real)0 : mom * (wself[i] * inv_npix);
+            const int per_ray = 4 * nrm;
+            Real val[4 * kMaxRadial / 64];
+#pragma unroll
+            for (int m = 0; m < 4 * kMaxRadial / 64; ++m) {
+                const int e = lane + 64 * m;
+                const int row = e / nrm, i = e - row * nrm;
+                Real v = (Real)0;
+                if (e < per_ray && row != Q_EPS && i < nr) {
+                    const Real mom = row == Q_A ? tB.x : row == Q_E ? tB.y : tB.z;
+                    v = mom * (wself[i] * inv_npix);
+                }
+                val[m] = v;
+            }
+            for (int k = wave; k < npix; k += WAVES) {
+                Real *dst = buf + (size_t)k * a.stride_k;
+#pragma unroll
+                for (int m = 0; m < 4 * kMaxRadial / 64; ++m)
+                    if (64 * m < per_ray && lane + 64 * m < per_ray) dst[lane + 64 * m] = val[m];
             }
             for (int k = tid; k < npix; k += WAVES * 64) top[k] = 0;
         }
@@ -897,7 +914,10 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
                     m &= m - 1;
                     if (seen % WAVES == wave) {
                         const int tk = __builtin_amdgcn_readlane(t, l);
-                        const double f = integrate_ray_wave<Real>(buf, (base + l) * a.stride_k, rd, rd2, nr, nrm, tk,
+                        const double f =
+                            nr > 64 ? integrate_ray_wave<Real, 2>(buf, (base + l) * a.stride_k, rd, rd2, nr, nrm, tk,
+                                                                  a.nside, a.zeta_g)
+                                    : integrate_ray_wave<Real, 1>(buf, (base + l) * a.stride_k, rd, rd2, nr, nrm, tk,
                                                                   a.nside, a.zeta_g);
                         if (lane == 0) fsum += f;
                     }
