@@ -37,7 +37,7 @@ class Domain(C.Structure):
 class Params(C.Structure):
     _fields_ = [("nside", C.c_int32), ("n_radial", C.c_int32), ("eta_r", C.c_double),
                 ("theta", C.c_double), ("alpha_b", C.c_double), ("subsample", C.c_int32),
-                ("zeta_g", C.c_int32)]
+                ("zeta_g", C.c_int32), ("theta_if", C.c_double), ("theta_src", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -119,6 +119,8 @@ def _c_params(p, **over):
     q.alpha_b = float(over.get("alpha_b", p.alpha_b))
     q.subsample = int(over.get("subsample", p.subsample))
     q.zeta_g = int(bool(over.get("zeta_g", p.zeta_g)))
+    q.theta_if = float(over.get("theta_if", getattr(p, "theta_if", 0.0)))
+    q.theta_src = float(over.get("theta_src", getattr(p, "theta_src", 0.0)))
     return q
 
 
@@ -252,7 +254,8 @@ def integrate_ray(r, eps, A, E, V, nside, zeta_g=True):
 
 
 def accepted(dom, params, n_h, xyz, q, target, f_prev=None, **over):
-    """Accepted nodes of one target: (lo_size [m,4], moments [m,8])."""
+    """Accepted nodes of one target: (lo_size [m,4], moments [m,9] =
+    eps, alpha, E, V, mass, com xyz, ionised mass)."""
     d, keep = _c_domain(dom)
     p = _c_params(params, **over)
     n_h = np.ascontiguousarray(n_h, dtype=np.float64)
@@ -262,7 +265,7 @@ def accepted(dom, params, n_h, xyz, q, target, f_prev=None, **over):
     cap = 1 << 16
     while True:
         ls = np.zeros((cap, 4), np.int64)
-        mom = np.zeros((cap, 8))
+        mom = np.zeros((cap, 9))
         n = lib().orc_accepted(C.byref(d), C.byref(p), _dp(n_h), len(q), _dp(xyz), _dp(q), _dp(fp),
                                int(target), cap, ls.ctypes.data_as(C.POINTER(C.c_int64)), _dp(mom))
         _check(n, "accepted")

@@ -184,7 +184,7 @@ int orc_deposit(const orc_domain *d, int64_t n_src, const double *src_xyz_cm,
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    double eps, alpha, erad, vol, mass;
+    double eps, alpha, erad, vol, mass, mion;
 } cellq_t;
 
 static void cell_quantities(const grid_t *g, const double *n_h, const double *ndot,
@@ -199,6 +199,9 @@ static void cell_quantities(const grid_t *g, const double *n_h, const double *nd
         out[c].erad = (f_prev ? f_prev[c] : 0.0) * dv;
         out[c].vol = dv;
         out[c].mass = n_h[c] * dv;
+        /* reading: a cell counts as ionised when its previous flux is
+         * positive (option (i) of Sec. 2.6); its gas is then ionised mass */
+        out[c].mion = (f_prev && f_prev[c] > 0) ? out[c].mass : 0.0;
     }
 }
 
@@ -216,7 +219,7 @@ typedef struct {
     int64_t child[8];             /* -1 = absent */
     int64_t cell;                 /* leaf cell, or -1 */
     int32_t level;
-    double eps, alpha, erad, vol, mass;
+    double eps, alpha, erad, vol, mass, mion;
     double mx[3], vx[3];          /* sums of mass * centre and volume * centre */
     double com[3];                /* finest units */
 } onode_t;
@@ -272,6 +275,7 @@ static int64_t tree_build(tree_t *t, const grid_t *g, const cellq_t *cq, const i
         x->erad = cq[c].erad;
         x->vol = cq[c].vol;
         x->mass = cq[c].mass;
+        x->mion = cq[c].mion;
         for (int a = 0; a < 3; ++a) {
             double ctr = (double)lo[a] + 0.5 * (double)size;
             x->mx[a] = cq[c].mass * ctr;
@@ -319,6 +323,7 @@ static int64_t tree_build(tree_t *t, const grid_t *g, const cellq_t *cq, const i
             x->erad += y->erad;
             x->vol += y->vol;
             x->mass += y->mass;
+            x->mion += y->mion;
             for (int a = 0; a < 3; ++a) {
                 x->mx[a] += y->mx[a];
                 x->vx[a] += y->vx[a];
@@ -638,6 +643,26 @@ static int walk_push(walk_t *w, int64_t id)
     return 0;
 }
 
+/* Squared limiting opening angle of a node (Sec. 2.4): theta_lim, lowered
+ * to theta_IF for a node holding an ionisation front (ionised mass strictly
+ * between delta_IF and 1 - delta_IF of its mass, delta_IF = 1e-8) and to
+ * theta_Src for a node holding emission (eps_n > 0).  A non-positive
+ * theta_IF or theta_Src switches that criterion off. */
+static double opening_angle2(const orc_params *p, const onode_t *x)
+{
+    const double dif = 1e-8;
+    double t2 = p->theta * p->theta;
+    if (p->theta_if > 0 && dif * x->mass < x->mion && x->mion < (1.0 - dif) * x->mass) {
+        double u = p->theta_if * p->theta_if;
+        if (u < t2) t2 = u;
+    }
+    if (p->theta_src > 0 && x->eps > 0) {
+        double u = p->theta_src * p->theta_src;
+        if (u < t2) t2 = u;
+    }
+    return t2;
+}
+
 static int walk_node(walk_t *w, int64_t id)
 {
     const onode_t *x = &w->t->n[id];
@@ -658,7 +683,7 @@ static int walk_node(walk_t *w, int64_t id)
             d2 += gc * gc;
         }
         double h = (double)x->size;
-        open = !(h * h < w->p->theta * w->p->theta * d2);
+        open = !(h * h < opening_angle2(w->p, x) * d2);
     }
     if (!open) return walk_push(w, id);
     for (int o = 0; o < 8; ++o)
@@ -940,9 +965,9 @@ int64_t orc_accepted(const orc_domain *d, const orc_params *p, const double *n_h
         const onode_t *x = &P.t.n[w.acc[q]];
         for (int a = 0; a < 3; ++a) lo_size_out[4 * q + a] = x->lo[a];
         lo_size_out[4 * q + 3] = x->size;
-        double *m = mom_out + 8 * q;
+        double *m = mom_out + 9 * q;
         m[0] = x->eps; m[1] = x->alpha; m[2] = x->erad; m[3] = x->vol; m[4] = x->mass;
-        m[5] = x->com[0]; m[6] = x->com[1]; m[7] = x->com[2];
+        m[5] = x->com[0]; m[6] = x->com[1]; m[7] = x->com[2]; m[8] = x->mion;
     }
     free(w.acc);
     prep_free(&P);

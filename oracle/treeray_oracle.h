@@ -32,6 +32,8 @@ typedef struct {
     double alpha_b;            /* Case-B recombination coefficient; 0 = optically thin */
     int32_t subsample;         /* s: s^3 angular sub-points per node */
     int32_t zeta_g;            /* 1: geometric correction as printed; 0: zeta_g = 1 */
+    double theta_if;           /* IF MAC opening angle (Sec. 2.4); <= 0: off */
+    double theta_src;          /* Src MAC opening angle (Sec. 2.4); <= 0: off */
 } orc_params;
 
 typedef struct {
@@ -89,12 +91,12 @@ void orc_wf3_weights(int32_t n, const double *r, double d, double *u_out);
 /* OTS integration of one ray; eps/A/E/V are the mapped totals */
 double orc_integrate_ray(int32_t n, const double *r, const double *eps, const double *A,
                          const double *E, const double *V, int32_t nside, int32_t zeta_g);
-/* accepted nodes of one target: lo3, size, occupied box, moments
- * (eps, alpha, E, V, mass, com3); returns count or <0 */
+/* accepted nodes of one target: lo3, size, moments (eps, alpha, E, V,
+ * mass, com3, ionised mass); returns count or <0 */
 int64_t orc_accepted(const orc_domain *d, const orc_params *p, const double *n_h,
                      int64_t n_src, const double *src_xyz_cm, const double *src_q,
                      const double *f_prev, int64_t target, int64_t max_out,
-                     int64_t *lo_size_out /* [max][4] */, double *mom_out /* [max][8] */);
+                     int64_t *lo_size_out /* [max][4] */, double *mom_out /* [max][9] */);
 
 #ifdef __cplusplus
 }

@@ -69,6 +69,8 @@ class Params:
     zeta_g: bool = True
     eps_lim: float = 1e-2
     max_iter: int = 30
+    theta_if: float = 0.0     # IF MAC opening angle; <= 0: off
+    theta_src: float = 0.0    # Src MAC opening angle; <= 0: off
 
 
 @dataclass
