@@ -80,6 +80,11 @@ typedef struct {
     int32_t max_iter;           /* outer iterations after the optically thin one */
     int32_t zeta_g;             /* 1: geometric correction of eq. (Rcorr:g); 0: zeta_g = 1 */
     tr_precision precision;
+    double theta_if;            /* IF MAC (Sec. 2.4): nodes whose ionised mass (cells with a
+                                   positive previous flux) lies strictly between 1e-8 and
+                                   1 - 1e-8 of their mass are accepted only below this
+                                   angle; <= 0 switches it off */
+    double theta_src;           /* Src MAC (Sec. 2.4): the same for nodes with eps_n > 0 */
 } tr_params;
 
 typedef struct {

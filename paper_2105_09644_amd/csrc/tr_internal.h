@@ -13,10 +13,13 @@ namespace tr {
 constexpr int kBlock = 8;          // cells per block edge
 constexpr int kMaxRadial = 128;    // evaluation points per ray (two 64-bit masks)
 constexpr int kMaxLevels = 24;
+constexpr int kGlobalList = 1 << 16;   // frontier / accepted-list entries of the fallback walk
 
 // Geometry flags packed into NodeGeo.w
 constexpr int kSizeMask = (1 << 24) - 1;
-constexpr int kPartialBit = 1 << 30;
+constexpr int kPartialBit = 1 << 30;   // node whose cells do not fill its cube
+constexpr int kIfBit = 1 << 28;        // node holds an ionisation front (IF MAC)
+constexpr int kSrcBit = 1 << 29;       // node holds emission (Src MAC)
 
 // Host-side topology of one domain in breadth-first order.
 struct DomTopo {

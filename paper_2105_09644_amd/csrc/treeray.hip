@@ -24,7 +24,7 @@
 namespace tr {
 
 // moment rows of the FP64 node arrays
-enum { MO_EPS = 0, MO_ALPHA, MO_E, MO_V, MO_MASS, MO_MX, MO_MY, MO_MZ, MO_VX, MO_VY, MO_VZ, MO_COUNT };
+enum { MO_EPS = 0, MO_ALPHA, MO_E, MO_V, MO_MASS, MO_MX, MO_MY, MO_MZ, MO_VX, MO_VY, MO_VZ, MO_MION, MO_COUNT };
 
 // ---------------------------------------------------------------------------
 // small utility kernels
@@ -134,6 +134,8 @@ __global__ void k_cell_quantities(int64_t n_cells, const double *__restrict__ n_
     M[MO_VX * nn + node] = dv * cx;
     M[MO_VY * nn + node] = dv * cy;
     M[MO_VZ * nn + node] = dv * cz;
+    // ionised gas: cells with a positive previous flux (the IF MAC's ionised mass)
+    M[MO_MION * nn + node] = fp > 0.0 ? mass : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -155,12 +157,23 @@ __global__ void k_reduce_level(int64_t b, int64_t e, const int2 *__restrict__ to
     }
 }
 
+// Node records for the sweep, and the node flags of the IF and Src MACs
+// (Sec. 2.4): an ionisation front when the ionised mass lies strictly between
+// 1e-8 and 1 - 1e-8 of the mass, emission when eps_n > 0.
 template <typename R, typename R4>
-__global__ void k_pack(int64_t nn, const double *__restrict__ M, R4 *__restrict__ A, R4 *__restrict__ B)
+__global__ void k_pack(int64_t nn, const double *__restrict__ M, R4 *__restrict__ A, R4 *__restrict__ B,
+                       int4 *__restrict__ geo)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     const double m = M[MO_MASS * nn + n], v = M[MO_V * nn + n];
+    {
+        const double mi = M[MO_MION * nn + n], dif = 1e-8;
+        int w = geo[n].w & ~(kIfBit | kSrcBit);
+        if (dif * m < mi && mi < (1.0 - dif) * m) w |= kIfBit;
+        if (M[MO_EPS * nn + n] > 0.0) w |= kSrcBit;
+        geo[n].w = w;
+    }
     double cx, cy, cz;
     if (m > 0.0) {
         cx = M[MO_MX * nn + n] / m;
@@ -206,10 +219,18 @@ struct SweepArgs {
     int32_t *queue;          // [0] next item, [1] overflow flag
     unsigned long long *stats;  // [0] accepted, [1] tested, [2] guard recomputes
     void *gbuf;              // ray buffers in global memory (when they do not fit in LDS)
-    double theta2;
+    double theta2, theta_if2, theta_src2;   // squared opening angles (0: criterion off)
     float guard_tol;
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
     int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
+    // walk lists too long for LDS: the target is queued in ovf (cell, output
+    // index) and a second launch (fallback = 1) walks it with per-workgroup
+    // lists of gfmax / gamax entries in device memory
+    int32_t fallback;
+    int64_t *ovf;
+    int32_t ovf_cap;
+    int32_t *glist;
+    int32_t gfmax, gamax;
 };
 
 // ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
@@ -679,7 +700,7 @@ __device__ inline void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATO
 enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_COUNT = 16 };
 
 __device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz, int *fr0, int *fr1, int *acc, int *sc,
-                            double &n_test)
+                            int fmax, int amax, double &n_test)
 {
     const int lane = lane_id();
     int *cur = fr0, *nxt = fr1;
@@ -710,7 +731,10 @@ __device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz
                     const double ddx = (double)(2 * g.x + sz - tx), ddy = (double)(2 * g.y + sz - ty),
                                  ddz = (double)(2 * g.z + sz - tz);
                     const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                    acc_it = a.theta2 * D2 > 4.0 * (double)sz * (double)sz;
+                    double th2 = a.theta2;   // lowered by the IF and Src MACs (Sec. 2.4)
+                    if ((g.w & kIfBit) && a.theta_if2 > 0.0) th2 = fmin(th2, a.theta_if2);
+                    if ((g.w & kSrcBit) && a.theta_src2 > 0.0) th2 = fmin(th2, a.theta_src2);
+                    acc_it = th2 * D2 > 4.0 * (double)sz * (double)sz;
                     open_it = !acc_it;
                 }
                 nch = open_it ? tp.y : 0;
@@ -721,7 +745,7 @@ __device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz
             const int cacc = __popcll(macc);
             int tot = 0;
             const int off = wave_excl_scan(nch, tot);
-            if (nacc + cacc > a.amax || nn + tot > a.fmax) {
+            if (nacc + cacc > amax || nn + tot > fmax) {
                 ovf = true;
                 break;
             }
@@ -771,12 +795,25 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
     p += nrm * sizeof(double);
     double *rd2 = (double *)p;  // 1 / (2 r_i)
     p += nrm * sizeof(double);
-    int *fr0 = (int *)p;
-    p += a.fmax * sizeof(int);
-    int *fr1 = (int *)p;
-    p += a.fmax * sizeof(int);
-    int *acc = (int *)p;
-    p += a.amax * sizeof(int);
+    int *fr0, *fr1, *acc;
+    int fmax, amax;
+    if (a.fallback) {
+        int *gl = a.glist + (size_t)blockIdx.x * (2 * (size_t)a.gfmax + a.gamax);
+        fmax = a.gfmax;
+        amax = a.gamax;
+        fr0 = gl;
+        fr1 = gl + fmax;
+        acc = gl + 2 * (size_t)fmax;
+    } else {
+        fmax = a.fmax;
+        amax = a.amax;
+        fr0 = (int *)p;
+        p += fmax * sizeof(int);
+        fr1 = (int *)p;
+        p += fmax * sizeof(int);
+        acc = (int *)p;
+        p += amax * sizeof(int);
+    }
     int *sc = (int *)p;
     p += S_COUNT * sizeof(int);
     double *red = (double *)p;
@@ -784,11 +821,14 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
     int *top = (int *)p;   // per ray: outermost point holding emission (0: none)
 
     double n_acc = 0, n_test = 0, n_guard = 0;
+    const int64_t n_items =
+        a.fallback ? (int64_t)min(__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
+                   : a.n_items;
 
     for (;;) {
         __syncthreads();
         if (tid == 0) {
-            sc[S_ITEM] = atomicAdd(&a.queue[0], 1);
+            sc[S_ITEM] = atomicAdd(&a.queue[a.fallback ? 2 : 0], 1);
             sc[S_AVAIL] = 0;
             sc[S_CLAIM] = 0;
             sc[S_DONE] = 0;
@@ -797,12 +837,19 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         }
         __syncthreads();
         const int64_t item = sc[S_ITEM];
-        if (item >= a.n_items) break;
-        const int64_t cell = a.targets ? a.targets[item] : (int64_t)a.order[item];
+        if (item >= n_items) break;
+        int64_t cell, o;   // target cell and its output index
+        if (a.fallback) {
+            cell = a.ovf[2 * item];
+            o = a.ovf[2 * item + 1];
+        } else {
+            cell = a.targets ? a.targets[item] : (int64_t)a.order[item];
+            o = a.targets ? item : cell;
+        }
         if (cell < 0 || cell >= a.n_cells) {
             if (tid == 0) {
-                a.f_out[item] = __longlong_as_double(0x7ff8000000000000ll);
-                if (a.ion_out) a.ion_out[item] = 0;
+                a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
+                if (a.ion_out) a.ion_out[o] = 0;
                 atomicOr(&a.queue[1], 2);
             }
             continue;
@@ -866,7 +913,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         __syncthreads();
 
         // --- wave 0 walks; every wave (wave 0 once its walk is done) maps ---
-        if (wave == 0) walk_target(a, D.root, tx, ty, tz, fr0, fr1, acc, sc, n_test);
+        if (wave == 0) walk_target(a, D.root, tx, ty, tz, fr0, fr1, acc, sc, fmax, amax, n_test);
         for (;;) {
             int start = 0;
             if (lane == 0) start = atomicAdd(&sc[S_CLAIM], CHUNK);
@@ -892,10 +939,20 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         __syncthreads();
         if (sc[S_OVF]) {
             if (tid == 0) {
-                const int64_t o = a.targets ? item : cell;
-                a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
-                if (a.ion_out) a.ion_out[o] = 0;
-                atomicOr(&a.queue[1], 1);
+                bool queued = false;
+                if (!a.fallback && a.ovf) {
+                    const int q = atomicAdd(&a.queue[3], 1);
+                    if (q < a.ovf_cap) {
+                        a.ovf[2 * q] = cell;
+                        a.ovf[2 * q + 1] = o;
+                        queued = true;
+                    }
+                }
+                if (!queued) {
+                    a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
+                    if (a.ion_out) a.ion_out[o] = 0;
+                    atomicOr(&a.queue[1], 1);
+                }
             }
             continue;
         }
@@ -939,7 +996,6 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
             for (int w = 0; w < WAVES; ++w) f += red[w];
             const double rtp = 0.5 * (double)tsize;
             f += 3.0 * (double)tA.w / (4.0 * kPi * rtp * rtp);
-            const int64_t o = a.targets ? item : cell;
             a.f_out[o] = f * D.flux_unit;
             if (a.ion_out) a.ion_out[o] = f > 0.0 ? 1 : 0;
         }
@@ -1099,6 +1155,9 @@ struct tr_ctx {
     int32_t *err_flags = nullptr;
     void *gbuf = nullptr;
     size_t gbuf_bytes = 0;
+    int32_t *glist = nullptr;            // walk lists of the fallback pass
+    int64_t *ovf = nullptr;              // targets queued for it: (cell, output index)
+    int64_t ovf_cap = 0;
     // delta scratch
     unsigned int *hist = nullptr;
     unsigned long long *dprefix = nullptr, *drank = nullptr, *dmax = nullptr;
@@ -1174,6 +1233,9 @@ void free_domains(tr_ctx *c)
     dfree(c->solve_tmp);
     dfree(c->gbuf);
     c->gbuf_bytes = 0;
+    dfree(c->glist);
+    dfree(c->ovf);
+    c->ovf_cap = 0;
     c->solve_tmp_n = 0;
     c->built = false;
 }
@@ -1185,6 +1247,8 @@ tr_status check_params(tr_ctx *c, const tr_params &p)
         return fail(c, TR_EINVAL, "n_radial must be 0 or in [3, 128]");
     if (p.n_radial == 0 && !(p.eta_r > 0)) return fail(c, TR_EINVAL, "eta_r must be > 0");
     if (!(p.theta >= 0) || !std::isfinite(p.theta)) return fail(c, TR_EINVAL, "theta must be >= 0");
+    if (!std::isfinite(p.theta_if) || !std::isfinite(p.theta_src))
+        return fail(c, TR_EINVAL, "theta_if and theta_src must be finite");
     if (!(p.alpha_b >= 0) || !std::isfinite(p.alpha_b)) return fail(c, TR_EINVAL, "alpha_b must be >= 0");
     if (p.subsample < 1 || p.subsample > 4) return fail(c, TR_EINVAL, "subsample must be in [1, 4]");
     if (p.max_iter < 0) return fail(c, TR_EINVAL, "max_iter must be >= 0");
@@ -1294,6 +1358,11 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     int64_t blocks = (int64_t)c->n_cu * L.per_cu;
     if (blocks > n_items) blocks = std::max<int64_t>(1, n_items);
     L.blocks = (int)blocks;
+    if (!c->glist) {
+        if (dalloc(c, (void **)&c->glist, sizeof(int32_t) * (size_t)c->n_cu * 3 * kGlobalList)) return TR_ENOMEM;
+        c->ovf_cap = std::min<int64_t>(std::max<int64_t>(c->n_cells, 1024), 1 << 20);
+        if (dalloc(c, (void **)&c->ovf, sizeof(int64_t) * 2 * (size_t)c->ovf_cap)) return TR_ENOMEM;
+    }
     if (!L.ldsbuf) {
         const size_t need = (size_t)L.blocks * npix * L.stride_k * real;
         if (need > c->gbuf_bytes) {
@@ -1338,6 +1407,8 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.stats = c->stats;
     a.gbuf = c->gbuf;
     a.theta2 = c->p.theta * c->p.theta;
+    a.theta_if2 = c->p.theta_if > 0.0 ? c->p.theta_if * c->p.theta_if : 0.0;
+    a.theta_src2 = c->p.theta_src > 0.0 ? c->p.theta_src * c->p.theta_src : 0.0;
     // guard band: 1e-5 N_side (at least 2e-5), several times the worst-case
     // FP32 error of the pixel-edge quantities (a few 1e-7 N_side)
     a.guard_tol = 1e-5f * std::max(2.0f, (float)c->p.nside);
@@ -1350,11 +1421,26 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.stride_k = L.stride_k;
     a.zeta_g = c->p.zeta_g;
     a.int_wave = L.intw ? 1 : 0;
+    a.fallback = 0;
+    a.ovf = c->ovf;
+    a.ovf_cap = (int32_t)c->ovf_cap;
+    a.glist = c->glist;
+    a.gfmax = kGlobalList;
+    a.gamax = kGlobalList;
     (void)hipGetLastError();   // a stale error of an earlier, unrelated call is not ours
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->queue, (int64_t)2, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->queue, (int64_t)4, 0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, c->stats, (int64_t)4);
     if (timed) HIPCHK(hipEventRecord(c->ev0, c->stream));
     hipLaunchKernelGGL(L.fn, dim3(L.blocks), dim3(L.waves * 64), L.lds, c->stream, a);
+    // the targets whose walk lists did not fit in LDS, again with lists in device memory
+    // (one workgroup per compute unit; it ends at once when none was queued)
+    {
+        SweepArgs b = a;
+        b.fallback = 1;
+        const size_t lds = sweep_lds_bytes(c->p.precision == TR_FP32C ? 4 : 8, a.npix, L.stride_k, c->nr_max, 0, 0,
+                                           L.waves, L.ldsbuf);
+        hipLaunchKernelGGL(L.fn, dim3(c->n_cu), dim3(L.waves * 64), lds, c->stream, b);
+    }
     HIPCHK(hipGetLastError());
     if (timed) {
         HIPCHK(hipEventRecord(c->ev1, c->stream));
@@ -1644,10 +1730,10 @@ tr_status enqueue_build(tr_ctx *c, const double *n_h, const double *f_prev, int3
     }
     if (c->p.precision == TR_FP32C)
         hipLaunchKernelGGL((k_pack<float, float4>), dim3(grid1(nn)), dim3(256), 0, c->stream, nn, c->mom, (float4 *)c->packA,
-                           (float4 *)c->packB);
+                           (float4 *)c->packB, c->geo);
     else
         hipLaunchKernelGGL((k_pack<double, double4>), dim3(grid1(nn)), dim3(256), 0, c->stream, nn, c->mom,
-                           (double4 *)c->packA, (double4 *)c->packB);
+                           (double4 *)c->packA, (double4 *)c->packB, c->geo);
     HIPCHK(hipGetLastError());
     return TR_OK;
 }

@@ -282,6 +282,38 @@ def test_graph_step_replays(T, orc):
         ctx.close()
 
 
+@pytest.mark.parametrize("theta_if,theta_src", [(0.25, 0.2), (1e-6, 1e-6)])
+def test_if_and_src_macs(T, orc, theta_if, theta_src):
+    """IF MAC and Src MAC (Sec. 2.4) against the oracle, on a previous flux that
+    holds an ionisation front (the oracle's absorbing sweep)."""
+    P = W.small_lognormal(16, n_src=2, seed=23)
+    f0, _ = orc_sweep(orc, P, thin=True)
+    f1, _ = orc_sweep(orc, P, f_prev=f0)
+    over = dict(theta_if=theta_if, theta_src=theta_src)
+    f2, i2 = orc_sweep(orc, P, f_prev=f1, **over)
+    for prec, tol in ((T.TR_FP64, TOL64), (T.TR_FP32C, TOL32)):
+        g2, j2, st = gpu_sweep(T, P, prec, f_prev=f1, **over)
+        compare(g2, j2, f2, i2, tol, front=None if prec == T.TR_FP64 else front_mask(P, f2),
+                name=f"macs {theta_if}/{theta_src} prec {prec}")
+        log(f"  accepted per target {st.nodes_accepted / P.total_cells():.1f}")
+    # thin, emission resolved to cells
+    t0, k0 = orc_sweep(orc, P, thin=True, theta_src=1e-6)
+    g0, j0, _ = gpu_sweep(T, P, T.TR_FP64, thin=True, theta_src=1e-6)
+    compare(g0, j0, t0, k0, TOL64, name="thin src mac fp64")
+
+
+def test_long_walks_use_device_lists(T, orc):
+    # theta = 0.05 on 16^3 accepts nearly every cell: the walk lists exceed
+    # the LDS capacity and every target goes through the device-memory pass
+    P = W.small_lognormal(16, n_src=2, seed=25)
+    f0, i0 = orc_sweep(orc, P, thin=True, theta=0.05)
+    for prec, tol in ((T.TR_FP64, TOL64), (T.TR_FP32C, TOL32)):
+        g0, j0, st = gpu_sweep(T, P, prec, thin=True, theta=0.05)
+        compare(g0, j0, f0, i0, tol, name=f"theta 0.05 prec {prec}")
+        assert st.overflow == 0
+        assert st.nodes_accepted / P.total_cells() > 2048
+
+
 def test_errors(T):
     P = W.small_uniform(16)
     ctx = T.context_for(P, T.TR_FP64)
