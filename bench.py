@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--launch-fp32c", default="", help="W,T,B launch shape of the FP32C sweep")
     ap.add_argument("--launch-fp64", default="", help="W,T,B launch shape of the FP64 sweep")
     ap.add_argument("--copy-mib", type=int, default=0, help="plain copies of this size after the steps")
+    ap.add_argument("--theta", type=float, default=None, help="override the opening angle")
+    ap.add_argument("--theta-if", type=float, default=None, help="IF MAC opening angle")
+    ap.add_argument("--theta-src", type=float, default=None, help="Src MAC opening angle")
     return ap.parse_args()
 
 
@@ -114,6 +117,9 @@ def main():
     torch.cuda.set_device(0)
     T.load_library()
     P = W.CONFIGS[args.config]()
+    for key in ("theta", "theta_if", "theta_src"):
+        if getattr(args, key) is not None:
+            setattr(P.params, key, getattr(args, key))
     npix = 12 * P.params.nside ** 2
     sub = P.params.subsample ** 3
     n_cells = P.total_cells()
@@ -230,7 +236,8 @@ def main():
         "dtype": main_form,
         "data": "synthetic",
         "config": {"workload": P.name, "cells": n_cells, "domains": len(P.domains), "n_pix": npix,
-                   "theta": P.params.theta, "n_radial_max": r["nr"],
+                   "theta": P.params.theta, "theta_if": P.params.theta_if, "theta_src": P.params.theta_src,
+                   "n_radial_max": r["nr"],
                    "precision": ("FP32 walk/weights/ray buffers, FP64 moments, ray integration and flux sums"
                                  if main_form == "f32" else "FP64 throughout")},
         "sweep_ms": round(r["sweep_ms"], 3),

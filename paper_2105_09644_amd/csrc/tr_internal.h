@@ -14,6 +14,7 @@ constexpr int kBlock = 8;          // cells per block edge
 constexpr int kMaxRadial = 128;    // evaluation points per ray (two 64-bit masks)
 constexpr int kMaxLevels = 24;
 constexpr int kGlobalList = 1 << 16;   // frontier / accepted-list entries of the fallback walk
+constexpr int kFallbackPerCu = 2;       // workgroups per compute unit in the fallback pass
 
 // Geometry flags packed into NodeGeo.w
 constexpr int kSizeMask = (1 << 24) - 1;

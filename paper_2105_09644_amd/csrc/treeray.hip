@@ -223,12 +223,12 @@ struct SweepArgs {
     float guard_tol;
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
     int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
-    // walk lists too long for LDS: the target is queued in ovf (cell, output
-    // index) and a second launch (fallback = 1) walks it with per-workgroup
-    // lists of gfmax / gamax entries in device memory
+    // walk lists too long for LDS: the item is queued in ovf and a second
+    // launch (fallback = 1) walks it with per-workgroup lists of gfmax / gamax
+    // entries in device memory
     int32_t fallback;
-    int64_t *ovf;
-    int32_t ovf_cap;
+    int32_t *ovf;
+    int64_t ovf_cap;
     int32_t *glist;
     int32_t gfmax, gamax;
 };
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
 
     double n_acc = 0, n_test = 0, n_guard = 0;
     const int64_t n_items =
-        a.fallback ? (int64_t)min(__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
+        a.fallback ? min((int64_t)__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
                    : a.n_items;
 
     for (;;) {
@@ -838,14 +838,9 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         __syncthreads();
         const int64_t item = sc[S_ITEM];
         if (item >= n_items) break;
-        int64_t cell, o;   // target cell and its output index
-        if (a.fallback) {
-            cell = a.ovf[2 * item];
-            o = a.ovf[2 * item + 1];
-        } else {
-            cell = a.targets ? a.targets[item] : (int64_t)a.order[item];
-            o = a.targets ? item : cell;
-        }
+        const int64_t it = a.fallback ? (int64_t)a.ovf[item] : item;
+        const int64_t cell = a.targets ? a.targets[it] : (int64_t)a.order[it];
+        const int64_t o = a.targets ? it : cell;   // output index
         if (cell < 0 || cell >= a.n_cells) {
             if (tid == 0) {
                 a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
@@ -943,8 +938,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
                 if (!a.fallback && a.ovf) {
                     const int q = atomicAdd(&a.queue[3], 1);
                     if (q < a.ovf_cap) {
-                        a.ovf[2 * q] = cell;
-                        a.ovf[2 * q + 1] = o;
+                        a.ovf[q] = (int32_t)item;
                         queued = true;
                     }
                 }
@@ -1156,7 +1150,7 @@ struct tr_ctx {
     void *gbuf = nullptr;
     size_t gbuf_bytes = 0;
     int32_t *glist = nullptr;            // walk lists of the fallback pass
-    int64_t *ovf = nullptr;              // targets queued for it: (cell, output index)
+    int32_t *ovf = nullptr;              // items queued for it
     int64_t ovf_cap = 0;
     // delta scratch
     unsigned int *hist = nullptr;
@@ -1358,10 +1352,14 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     int64_t blocks = (int64_t)c->n_cu * L.per_cu;
     if (blocks > n_items) blocks = std::max<int64_t>(1, n_items);
     L.blocks = (int)blocks;
-    if (!c->glist) {
-        if (dalloc(c, (void **)&c->glist, sizeof(int32_t) * (size_t)c->n_cu * 3 * kGlobalList)) return TR_ENOMEM;
-        c->ovf_cap = std::min<int64_t>(std::max<int64_t>(c->n_cells, 1024), 1 << 20);
-        if (dalloc(c, (void **)&c->ovf, sizeof(int64_t) * 2 * (size_t)c->ovf_cap)) return TR_ENOMEM;
+    if (!c->glist &&
+        dalloc(c, (void **)&c->glist, sizeof(int32_t) * (size_t)c->n_cu * kFallbackPerCu * 3 * kGlobalList))
+        return TR_ENOMEM;
+    if (c->ovf_cap < n_items) {   // every item may need the second pass
+        dfree(c->ovf);
+        c->ovf_cap = 0;
+        if (dalloc(c, (void **)&c->ovf, sizeof(int32_t) * (size_t)n_items)) return TR_ENOMEM;
+        c->ovf_cap = n_items;
     }
     if (!L.ldsbuf) {
         const size_t need = (size_t)L.blocks * npix * L.stride_k * real;
@@ -1423,7 +1421,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.int_wave = L.intw ? 1 : 0;
     a.fallback = 0;
     a.ovf = c->ovf;
-    a.ovf_cap = (int32_t)c->ovf_cap;
+    a.ovf_cap = c->ovf_cap;
     a.glist = c->glist;
     a.gfmax = kGlobalList;
     a.gamax = kGlobalList;
@@ -1439,7 +1437,8 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
         b.fallback = 1;
         const size_t lds = sweep_lds_bytes(c->p.precision == TR_FP32C ? 4 : 8, a.npix, L.stride_k, c->nr_max, 0, 0,
                                            L.waves, L.ldsbuf);
-        hipLaunchKernelGGL(L.fn, dim3(c->n_cu), dim3(L.waves * 64), lds, c->stream, b);
+        hipLaunchKernelGGL(L.fn, dim3(c->n_cu * std::min(L.per_cu, kFallbackPerCu)), dim3(L.waves * 64), lds,
+                           c->stream, b);
     }
     HIPCHK(hipGetLastError());
     if (timed) {
