@@ -224,9 +224,8 @@ struct SweepArgs {
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
     int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
     // walk lists too long for LDS: the item is queued in ovf and a second
-    // launch (fallback = 1) walks it with per-workgroup lists of gfmax / gamax
-    // entries in device memory
-    int32_t fallback;
+    // launch (k_sweep_fallback) walks it with per-workgroup lists of gfmax /
+    // gamax entries in device memory
     int32_t *ovf;
     int64_t ovf_cap;
     int32_t *glist;
@@ -768,8 +767,10 @@ __device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz
     }
 }
 
-template <typename Real, int WAVES, bool LDSBUF>
-__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
+// The sweep of one launch.  FALLBACK: the second pass over the items whose
+// walk lists did not fit in LDS, with the lists in device memory.
+template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK>
+__device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     using R4 = typename R4T<Real>::T;
     constexpr bool ATOMIC = WAVES > 1;
@@ -797,7 +798,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
     p += nrm * sizeof(double);
     int *fr0, *fr1, *acc;
     int fmax, amax;
-    if (a.fallback) {
+    if (FALLBACK) {
         int *gl = a.glist + (size_t)blockIdx.x * (2 * (size_t)a.gfmax + a.gamax);
         fmax = a.gfmax;
         amax = a.gamax;
@@ -822,13 +823,13 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
 
     double n_acc = 0, n_test = 0, n_guard = 0;
     const int64_t n_items =
-        a.fallback ? min((int64_t)__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
+        FALLBACK ? min((int64_t)__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
                    : a.n_items;
 
     for (;;) {
         __syncthreads();
         if (tid == 0) {
-            sc[S_ITEM] = atomicAdd(&a.queue[a.fallback ? 2 : 0], 1);
+            sc[S_ITEM] = atomicAdd(&a.queue[FALLBACK ? 2 : 0], 1);
             sc[S_AVAIL] = 0;
             sc[S_CLAIM] = 0;
             sc[S_DONE] = 0;
@@ -838,7 +839,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         __syncthreads();
         const int64_t item = sc[S_ITEM];
         if (item >= n_items) break;
-        const int64_t it = a.fallback ? (int64_t)a.ovf[item] : item;
+        const int64_t it = FALLBACK ? (int64_t)a.ovf[item] : item;
         const int64_t cell = a.targets ? a.targets[it] : (int64_t)a.order[it];
         const int64_t o = a.targets ? it : cell;   // output index
         if (cell < 0 || cell >= a.n_cells) {
@@ -935,7 +936,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         if (sc[S_OVF]) {
             if (tid == 0) {
                 bool queued = false;
-                if (!a.fallback && a.ovf) {
+                if (!FALLBACK && a.ovf) {
                     const int q = atomicAdd(&a.queue[3], 1);
                     if (q < a.ovf_cap) {
                         a.ovf[q] = (int32_t)item;
@@ -1002,6 +1003,18 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
         if (n_test > 0) atomicAdd(&a.stats[1], (unsigned long long)n_test);
         if (n_guard > 0) atomicAdd(&a.stats[2], (unsigned long long)n_guard);
     }
+}
+
+template <typename Real, int WAVES, bool LDSBUF>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
+{
+    sweep_body<Real, WAVES, LDSBUF, false>(a);
+}
+
+template <typename Real, int WAVES, bool LDSBUF>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_fallback(SweepArgs a)
+{
+    sweep_body<Real, WAVES, LDSBUF, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1288,10 +1301,12 @@ constexpr size_t kLdsMax = 160 * 1024;
 using KernelFn = void (*)(SweepArgs);
 
 template <typename Real>
-KernelFn pick_kernel(int waves, bool ldsbuf)
+KernelFn pick_kernel(int waves, bool ldsbuf, bool fallback)
 {
-#define TR_CASE(W)                                                    \
-    case W:                                                           \
+#define TR_CASE(W)                                                                                      \
+    case W:                                                                                             \
+        if (fallback)                                                                                   \
+            return ldsbuf ? (KernelFn)k_sweep_fallback<Real, W, true> : (KernelFn)k_sweep_fallback<Real, W, false>; \
         return ldsbuf ? (KernelFn)k_sweep<Real, W, true> : (KernelFn)k_sweep<Real, W, false>;
     switch (waves) {
         TR_CASE(1)
@@ -1306,7 +1321,7 @@ KernelFn pick_kernel(int waves, bool ldsbuf)
 }
 
 struct LaunchPlan {
-    KernelFn fn = nullptr;
+    KernelFn fn = nullptr, fn_fb = nullptr;
     int waves = 0, blocks = 0, per_cu = 0, fmax = 0, amax = 0, stride_k = 0;
     size_t lds = 0;
     bool ldsbuf = true;
@@ -1338,9 +1353,11 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
         L.amax = 4096;
     }
     L.lds = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, L.amax, waves, L.ldsbuf);
-    L.fn = f32 ? pick_kernel<float>(waves, L.ldsbuf) : pick_kernel<double>(waves, L.ldsbuf);
-    if (!L.fn) return fail(c, TR_EINVAL, "waves per target must be 1, 2, 4, 8 or 16");
+    L.fn = f32 ? pick_kernel<float>(waves, L.ldsbuf, false) : pick_kernel<double>(waves, L.ldsbuf, false);
+    L.fn_fb = f32 ? pick_kernel<float>(waves, L.ldsbuf, true) : pick_kernel<double>(waves, L.ldsbuf, true);
+    if (!L.fn || !L.fn_fb) return fail(c, TR_EINVAL, "waves per target must be 1, 2, 4, 8 or 16");
     HIPCHK(hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
+    HIPCHK(hipFuncSetAttribute((const void *)L.fn_fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
     int occ = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)L.fn, waves * 64, L.lds));
     if (occ <= 0) return fail(c, TR_EINVAL, "sweep kernel does not fit on a compute unit (LDS " + std::to_string(L.lds) + " B)");
@@ -1419,7 +1436,6 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.stride_k = L.stride_k;
     a.zeta_g = c->p.zeta_g;
     a.int_wave = L.intw ? 1 : 0;
-    a.fallback = 0;
     a.ovf = c->ovf;
     a.ovf_cap = c->ovf_cap;
     a.glist = c->glist;
@@ -1433,12 +1449,10 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     // the targets whose walk lists did not fit in LDS, again with lists in device memory
     // (one workgroup per compute unit; it ends at once when none was queued)
     {
-        SweepArgs b = a;
-        b.fallback = 1;
         const size_t lds = sweep_lds_bytes(c->p.precision == TR_FP32C ? 4 : 8, a.npix, L.stride_k, c->nr_max, 0, 0,
                                            L.waves, L.ldsbuf);
-        hipLaunchKernelGGL(L.fn, dim3(c->n_cu * std::min(L.per_cu, kFallbackPerCu)), dim3(L.waves * 64), lds,
-                           c->stream, b);
+        hipLaunchKernelGGL(L.fn_fb, dim3(c->n_cu * std::min(L.per_cu, kFallbackPerCu)), dim3(L.waves * 64), lds,
+                           c->stream, a);
     }
     HIPCHK(hipGetLastError());
     if (timed) {
