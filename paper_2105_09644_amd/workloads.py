@@ -292,6 +292,73 @@ def small_amr(nroot: int = 2, seed: int = 0, threshold: float = 150.0,
     return Problem(f"amr{nroot}_{seed}", [dom], [nh], [xyz], [q], p)
 
 
+# --------------------------------------------------------------------------
+# Static radiation-only set-ups of the paper's accuracy tests (Sec. 3)
+# --------------------------------------------------------------------------
+
+M_P = 1.67262192e-24          # proton mass, g
+X_H = 0.70                    # hydrogen mass fraction of the paper's gas (Sec. 3.1)
+
+
+def hydrogen_density(rho_g_cm3: float) -> float:
+    """n_H of gas with mass density rho and hydrogen mass fraction X_H."""
+    return X_H * rho_g_cm3 / M_P
+
+
+def cell_centres_pc(dom: Domain, origin_pc=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Centres (pc) of a uniform domain's cells in the library's cell order."""
+    e = dom.extent_finest()
+    dx = dom.finest_dx_cm() / PC_CM
+    axes = [origin_pc[a] + (np.arange(e[a]) + 0.5) * dx for a in range(3)]
+    x, y, z = np.meshgrid(*axes, indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+def two_source_cloud(n: int = 128, nside: int = 2, theta: float = 0.5, theta_if: float = 0.0,
+                     theta_src: float = 0.0) -> Problem:
+    """Cloud irradiated by two sources (Sec. 3.4): the domain spans
+    [-2, 4] x [-2, 4] x [-3, 3] pc; a cloud of radius 0.5 pc and density
+    2.6e-21 g/cm^3 at the origin in gas of 1e-24 g/cm^3; two sources of
+    3.2e48 photons/s at (-2, 0, 0) and (0, -2, 0) pc, on the domain's faces.
+    The set-up is symmetric about the plane x = y."""
+    dom = uniform_domain(n, box_pc=6.0)
+    origin = (-2.0, -2.0, -3.0)
+    c = cell_centres_pc(dom, origin)
+    r2 = np.sum(c ** 2, axis=1)
+    nh = np.where(r2 < 0.5 ** 2, hydrogen_density(2.6e-21), hydrogen_density(1e-24))
+    src_pc = np.array([[-2.0, 0.0, 0.0], [0.0, -2.0, 0.0]])
+    xyz = (src_pc - np.array(origin)) * PC_CM
+    p = Params(nside=nside, n_radial=0, eta_r=2.0, theta=theta, theta_if=theta_if, theta_src=theta_src)
+    return Problem(f"two_source_cloud{n}", [dom], [nh], [xyz], [np.array([3.2e48, 3.2e48])], p)
+
+
+def rabbit_hole(width_pc: float, n_long: int = 384, axis: int = 0, nside: int = 4, theta: float = 0.25,
+                theta_if: float = 0.0, theta_src: float = 0.0) -> Problem:
+    """Rabbit hole (Sec. 3.2.1): a 6 x 2 x 2 pc box of cold dense gas
+    (1e-18 g/cm^3) pierced along its long axis by a hole of square cross-section
+    width_pc filled with warm rarefied gas (1e-24 g/cm^3); a source of 1e49
+    photons/s at the hole's entrance, the centre of one 2 x 2 pc face.  The long
+    axis is x (axis 0) or z (axis 2); cells are cubes, n_long along it."""
+    nb = n_long // BLOCK
+    nroot = [nb // 3] * 3
+    nroot[axis] = nb
+    dom = Domain(nroot=tuple(nroot), root_block_cm=6.0 * PC_CM / nb)
+    e = dom.extent_finest()
+    dx = dom.finest_dx_cm() / PC_CM
+    origin = [-1.0, -1.0, -1.0]
+    origin[axis] = 0.0
+    axes = [origin[a] + (np.arange(e[a]) + 0.5) * dx for a in range(3)]
+    g = np.meshgrid(*axes, indexing="ij")
+    inside = np.ones(g[0].shape, bool)
+    for a in range(3):
+        if a != axis:
+            inside &= np.abs(g[a]) < 0.5 * width_pc
+    nh = np.where(inside, hydrogen_density(1e-24), hydrogen_density(1e-18)).ravel()
+    xyz = (np.zeros(3) - np.array(origin)) * PC_CM
+    p = Params(nside=nside, n_radial=0, eta_r=2.0, theta=theta, theta_if=theta_if, theta_src=theta_src)
+    return Problem(f"rabbit_hole_w{width_pc:g}_axis{axis}", [dom], [nh], [xyz[None, :]], [np.array([1e49])], p)
+
+
 def prev_flux_field(problem: Problem, seed: int = 0, dark_fraction: float = 0.2,
                     sigma: float = 1.0) -> np.ndarray:
     """Synthetic previous-iteration flux for every cell of ``problem``, an input
