@@ -37,7 +37,8 @@ class Domain(C.Structure):
 class Params(C.Structure):
     _fields_ = [("nside", C.c_int32), ("n_radial", C.c_int32), ("eta_r", C.c_double),
                 ("theta", C.c_double), ("alpha_b", C.c_double), ("subsample", C.c_int32),
-                ("zeta_g", C.c_int32), ("theta_if", C.c_double), ("theta_src", C.c_double)]
+                ("zeta_g", C.c_int32), ("theta_if", C.c_double), ("theta_src", C.c_double),
+                ("src_radius_cm", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -66,6 +67,9 @@ def lib():
         L.orc_solve.argtypes = [C.POINTER(Domain), C.POINTER(Params), dp, C.c_int64, dp, dp,
                                 C.c_double, C.c_int32, dp, u8p, C.POINTER(C.c_int32), dp]
         L.orc_deposit.argtypes = [C.POINTER(Domain), C.c_int64, dp, dp, dp]
+        L.orc_deposit_spheres.argtypes = [C.POINTER(Domain), C.c_int64, dp, dp, C.c_double, dp]
+        L.orc_ball_box_volume.restype = C.c_double
+        L.orc_ball_box_volume.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_delta_cell.restype = C.c_double
         L.orc_delta_cell.argtypes = [C.c_int64, dp, dp]
         L.orc_delta_tot.restype = C.c_double
@@ -121,6 +125,7 @@ def _c_params(p, **over):
     q.zeta_g = int(bool(over.get("zeta_g", p.zeta_g)))
     q.theta_if = float(over.get("theta_if", getattr(p, "theta_if", 0.0)))
     q.theta_src = float(over.get("theta_src", getattr(p, "theta_src", 0.0)))
+    q.src_radius_cm = float(over.get("src_radius_cm", getattr(p, "src_radius_cm", 0.0)))
     return q
 
 
@@ -153,14 +158,26 @@ def radial_points(dom, params, **over):
     return r[:n].copy()
 
 
-def deposit(dom, xyz, q):
+def deposit(dom, xyz, q, radius_cm=0.0):
+    """Source rates per cell; radius_cm > 0: sources are uniform spheres."""
     n = cell_count(dom)
     d, keep = _c_domain(dom)
     out = np.zeros(n)
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.float64)
-    _check(lib().orc_deposit(C.byref(d), len(q), _dp(xyz), _dp(q), _dp(out)), "deposit")
+    if radius_cm > 0:
+        _check(lib().orc_deposit_spheres(C.byref(d), len(q), _dp(xyz), _dp(q), float(radius_cm), _dp(out)),
+               "deposit")
+    else:
+        _check(lib().orc_deposit(C.byref(d), len(q), _dp(xyz), _dp(q), _dp(out)), "deposit")
     return out
+
+
+def ball_box_volume(centre, radius, lo, hi):
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    return float(lib().orc_ball_box_volume(float(centre[0]), float(centre[1]), float(centre[2]), float(radius),
+                                           _dp(lo), _dp(hi)))
 
 
 def sweep(dom, params, n_h, xyz, q, f_prev=None, targets=None, **over):

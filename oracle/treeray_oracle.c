@@ -118,6 +118,169 @@ int orc_cell_geometry(const orc_domain *d, int64_t *lo3, int64_t *size)
  * to lie on it.                                                             */
 /* ------------------------------------------------------------------------ */
 
+/* Finite-radius sources (Sec. 2.7: sources are mapped as uniform spheres).
+ * reading: a source of radius R gives each cell the share of its rate equal
+ * to the part of the sphere's volume inside the cell, normalised to the
+ * volume inside the domain.  The volume of a ball cut by a box is the
+ * integral over z of the area of a disk cut by a rectangle; the area is
+ * exact, the integral Gauss-Legendre between the heights where the area
+ * stops being smooth.                                                       */
+
+/* area of the part of the disk of radius r (centre 0) with x >= u, y >= v */
+static double quad_area(double r, double u, double v)
+{
+    if (u < 0) return 2.0 * quad_area(r, 0.0, v) - quad_area(r, -u, v);
+    if (v < 0) return 2.0 * quad_area(r, u, 0.0) - quad_area(r, u, -v);
+    if (u * u + v * v >= r * r) return 0.0;
+    double x1 = sqrt(r * r - v * v);
+    /* integral of sqrt(r^2 - x^2) - v over [u, x1] */
+    double hu = 0.5 * (u * sqrt(fmax(r * r - u * u, 0.0)) + r * r * asin(fmin(u / r, 1.0)));
+    double h1 = 0.5 * (x1 * sqrt(fmax(r * r - x1 * x1, 0.0)) + r * r * asin(fmin(x1 / r, 1.0)));
+    return h1 - hu - v * (x1 - u);
+}
+
+typedef struct {
+    double cz, R;              /* sphere centre height and radius */
+    double x0, x1, y0, y1;     /* rectangle relative to the sphere's centre */
+} slab_t;
+
+static double slab_area(const slab_t *S, double z)
+{
+    double h = z - S->cz;
+    double r2 = S->R * S->R - h * h;
+    if (r2 <= 0) return 0.0;
+    double r = sqrt(r2);
+    return quad_area(r, S->x0, S->y0) - quad_area(r, S->x1, S->y0) - quad_area(r, S->x0, S->y1) +
+           quad_area(r, S->x1, S->y1);
+}
+
+/* Gauss-Legendre nodes and weights on [0, 1], n points (Newton on P_n) */
+#define GL_N 24
+static double gl_x[GL_N], gl_w[GL_N];
+static int gl_ready = 0;
+static void gl_init(void)
+{
+    for (int i = 0; i < GL_N; ++i) {
+        double x = cos(ORC_PI * (i + 0.75) / (GL_N + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= GL_N; ++k) {
+                double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            dp = GL_N * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        gl_x[i] = 0.5 * (1.0 - x);
+        gl_w[i] = 1.0 / ((1.0 - x * x) * dp * dp);   /* weight on [-1, 1] is 2/(...), halved for [0, 1] */
+    }
+    gl_ready = 1;
+}
+
+static int cmp_dbl(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* The disk area is smooth in z except where the circle meets a rectangle
+ * edge line or corner; the integral is split there, and on each piece the
+ * substitution z = p + (q - p)(1 - cos(pi t))/2 removes the (z - z*)^(3/2)
+ * behaviour at its ends before Gauss-Legendre quadrature in t.            */
+double orc_ball_box_volume(double cx, double cy, double cz, double R, const double *lo, const double *hi)
+{
+#pragma omp critical(orc_gl)
+    {
+        if (!gl_ready) gl_init();
+    }
+    double za = fmax(lo[2], cz - R), zb = fmin(hi[2], cz + R);
+    if (!(R > 0) || za >= zb || lo[0] >= cx + R || hi[0] <= cx - R || lo[1] >= cy + R || hi[1] <= cy - R)
+        return 0.0;
+    slab_t S = {cz, R, lo[0] - cx, hi[0] - cx, lo[1] - cy, hi[1] - cy};
+    double d[8] = {fabs(S.x0), fabs(S.x1), fabs(S.y0), fabs(S.y1), hypot(S.x0, S.y0), hypot(S.x1, S.y0),
+                   hypot(S.x0, S.y1), hypot(S.x1, S.y1)};
+    double cut[18];
+    int nc = 0;
+    cut[nc++] = za;
+    cut[nc++] = zb;
+    for (int k = 0; k < 8; ++k)
+        if (d[k] < R) {
+            double h = sqrt(R * R - d[k] * d[k]);
+            if (cz - h > za && cz - h < zb) cut[nc++] = cz - h;
+            if (cz + h > za && cz + h < zb) cut[nc++] = cz + h;
+        }
+    qsort(cut, (size_t)nc, sizeof(double), cmp_dbl);
+    double v = 0.0;
+    for (int k = 0; k + 1 < nc; ++k) {
+        double p = cut[k], q = cut[k + 1];
+        if (!(q > p)) continue;
+        double sum = 0.0;
+        for (int i = 0; i < GL_N; ++i) {
+            double t = gl_x[i];
+            double z = p + (q - p) * 0.5 * (1.0 - cos(ORC_PI * t));
+            sum += gl_w[i] * slab_area(&S, z) * sin(ORC_PI * t);
+        }
+        v += sum * (q - p) * 0.5 * ORC_PI;
+    }
+    return v;
+}
+
+static int deposit_spheres(const grid_t *g, int64_t n_src, const double *xyz, const double *q, double radius,
+                           double *ndot)
+{
+    const double R = radius / g->dx;   /* finest-cell units */
+    int64_t **hit = (int64_t **)calloc((size_t)(n_src > 0 ? n_src : 1), sizeof(int64_t *));
+    double **vol = (double **)calloc((size_t)(n_src > 0 ? n_src : 1), sizeof(double *));
+    int64_t *nhit = (int64_t *)calloc((size_t)(n_src > 0 ? n_src : 1), sizeof(int64_t));
+    if (!hit || !vol || !nhit) { free(hit); free(vol); free(nhit); return -2; }
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
+    for (int64_t s = 0; s < n_src; ++s) {
+        double u[3];
+        for (int a = 0; a < 3; ++a) {
+            u[a] = xyz[3 * s + a] / g->dx;
+            if (u[a] < 0 || u[a] > (double)g->ext[a]) bad = 1;
+        }
+        if (!(q[s] >= 0) || !isfinite(q[s])) bad = 1;
+        if (bad) continue;
+        int64_t cap = 64;
+        hit[s] = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        vol[s] = (double *)malloc(sizeof(double) * (size_t)cap);
+        for (int64_t c = 0; c < g->n && hit[s]; ++c) {
+            const int64_t *lo = g->lo + 3 * c;
+            double clo[3], chi[3];
+            for (int a = 0; a < 3; ++a) {
+                clo[a] = (double)lo[a];
+                chi[a] = (double)(lo[a] + g->size[c]);
+            }
+            double v = orc_ball_box_volume(u[0], u[1], u[2], R, clo, chi);
+            if (v <= 0) continue;
+            if (nhit[s] == cap) {
+                cap *= 2;
+                hit[s] = (int64_t *)realloc(hit[s], sizeof(int64_t) * (size_t)cap);
+                vol[s] = (double *)realloc(vol[s], sizeof(double) * (size_t)cap);
+                if (!hit[s] || !vol[s]) { bad = 1; break; }
+            }
+            hit[s][nhit[s]] = c;
+            vol[s][nhit[s]] = v;
+            nhit[s]++;
+        }
+        if (nhit[s] == 0) bad = 1;
+    }
+    memset(ndot, 0, sizeof(double) * (size_t)g->n);
+    for (int64_t s = 0; s < n_src && !bad; ++s) {
+        double tot = 0;
+        for (int64_t m = 0; m < nhit[s]; ++m) tot += vol[s][m];
+        for (int64_t m = 0; m < nhit[s]; ++m) ndot[hit[s][m]] += q[s] * (vol[s][m] / tot);
+    }
+    for (int64_t s = 0; s < n_src; ++s) { free(hit[s]); free(vol[s]); }
+    free(hit); free(vol); free(nhit);
+    return bad ? -1 : 0;
+}
+
 static int cell_contains(const grid_t *g, int64_t c, const double u[3])
 {
     const int64_t *lo = g->lo + 3 * c;
@@ -171,6 +334,16 @@ int orc_deposit(const orc_domain *d, int64_t n_src, const double *src_xyz_cm,
     grid_t g;
     int rc = grid_make(d, &g);
     if (!rc) rc = deposit(&g, n_src, src_xyz_cm, src_q, ndot_out);
+    grid_free(&g);
+    return rc;
+}
+
+int orc_deposit_spheres(const orc_domain *d, int64_t n_src, const double *src_xyz_cm, const double *src_q,
+                        double radius_cm, double *ndot_out)
+{
+    grid_t g;
+    int rc = grid_make(d, &g);
+    if (!rc) rc = deposit_spheres(&g, n_src, src_xyz_cm, src_q, radius_cm, ndot_out);
     grid_free(&g);
     return rc;
 }
@@ -880,7 +1053,8 @@ static int prep(const orc_domain *d, const orc_params *p, const double *n_h, int
     double *ndot = (double *)malloc(sizeof(double) * (size_t)P->g.n);
     P->cq = (cellq_t *)malloc(sizeof(cellq_t) * (size_t)P->g.n);
     if (!ndot || !P->cq) { free(ndot); return -2; }
-    rc = deposit(&P->g, n_src, xyz, q, ndot);
+    rc = p->src_radius_cm > 0 ? deposit_spheres(&P->g, n_src, xyz, q, p->src_radius_cm, ndot)
+                              : deposit(&P->g, n_src, xyz, q, ndot);
     if (rc) { free(ndot); return rc; }
     cell_quantities(&P->g, n_h, ndot, f_prev, p->alpha_b, P->cq);
     free(ndot);

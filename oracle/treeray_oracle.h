@@ -34,6 +34,7 @@ typedef struct {
     int32_t zeta_g;            /* 1: geometric correction as printed; 0: zeta_g = 1 */
     double theta_if;           /* IF MAC opening angle (Sec. 2.4); <= 0: off */
     double theta_src;          /* Src MAC opening angle (Sec. 2.4); <= 0: off */
+    double src_radius_cm;      /* > 0: sources are uniform spheres of this radius (Sec. 2.7) */
 } orc_params;
 
 typedef struct {
@@ -75,6 +76,12 @@ double orc_delta_tot(int64_t n, const double *f_new, const double *f_old, const 
 /* point-source rates per cell */
 int orc_deposit(const orc_domain *d, int64_t n_src, const double *src_xyz_cm,
                 const double *src_q, double *ndot_out);
+
+/* sources as uniform spheres of radius_cm: rates split by the sphere volume in each cell */
+int orc_deposit_spheres(const orc_domain *d, int64_t n_src, const double *src_xyz_cm,
+                        const double *src_q, double radius_cm, double *ndot_out);
+/* volume of the ball (centre, R) inside the box [lo, hi] */
+double orc_ball_box_volume(double cx, double cy, double cz, double R, const double *lo, const double *hi);
 
 /* OpenMP threads a sweep uses */
 int32_t orc_num_threads(void);

@@ -71,6 +71,7 @@ class Params:
     max_iter: int = 30
     theta_if: float = 0.0     # IF MAC opening angle; <= 0: off
     theta_src: float = 0.0    # Src MAC opening angle; <= 0: off
+    src_radius_cm: float = 0.0   # > 0: sources are uniform spheres of this radius
 
 
 @dataclass
