@@ -85,6 +85,9 @@ typedef struct {
                                    1 - 1e-8 of their mass are accepted only below this
                                    angle; <= 0 switches it off */
     double theta_src;           /* Src MAC (Sec. 2.4): the same for nodes with eps_n > 0 */
+    double src_radius_cm;       /* > 0: sources are uniform spheres of this radius (Sec. 2.7),
+                                   each cell taking the share of the rate equal to its part of
+                                   the sphere's in-domain volume; 0: point sources */
 } tr_params;
 
 typedef struct {
@@ -113,9 +116,12 @@ tr_status tr_set_domains(tr_ctx *c, int32_t n_domains, const tr_domain *doms);
 /* Leaf cells of domain dom (dom = -1: all domains together). */
 tr_status tr_cell_count(const tr_ctx *c, int32_t dom, int64_t *n_cells);
 
-/* Point sources of domain dom: xyz_cm[n][3] relative to the domain's low
- * corner, q[n] photons/s (Sec. 2.7).  Each rate is split equally over the
- * leaf cells whose closed extent contains the point. */
+/* Sources of domain dom: xyz_cm[n][3] relative to the domain's low corner,
+ * q[n] photons/s (Sec. 2.7).  With src_radius_cm = 0 each rate is split
+ * equally over the leaf cells whose closed extent contains the point;
+ * otherwise by the exact volume of the source sphere in each cell (a
+ * sphere reaching more than 16 finest cells may stop the build with a
+ * deposit error). */
 tr_status tr_set_sources(tr_ctx *c, int32_t dom, int64_t n, const double *xyz_cm,
                          const double *q_per_s);
 

@@ -15,6 +15,7 @@ constexpr int kMaxRadial = 128;    // evaluation points per ray (two 64-bit mask
 constexpr int kMaxLevels = 24;
 constexpr int kGlobalList = 1 << 16;   // frontier / accepted-list entries of the fallback walk
 constexpr int kFallbackPerCu = 2;       // workgroups per compute unit in the fallback pass
+constexpr int kGlNodes = 24;            // Gauss-Legendre nodes of the sphere-deposit quadrature
 
 // Geometry flags packed into NodeGeo.w
 constexpr int kSizeMask = (1 << 24) - 1;

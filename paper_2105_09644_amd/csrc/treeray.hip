@@ -97,6 +97,134 @@ __global__ void k_deposit(const double *__restrict__ xyz, const double *__restri
     for (int c = 0; c < nc; ++c) atomicAdd(&ndot[cells[c]], share);
 }
 
+// Sources as uniform spheres (Sec. 2.7): each leaf cell receives the rate
+// times the fraction of the sphere's in-domain volume that lies inside it.
+// Volume of a ball cut by a box = integral over z of the area of a disk cut
+// by a rectangle; that area is exact, and the integral is split where the
+// circle meets an edge line or a corner of the rectangle (the area's
+// derivatives jump there) and taken on each piece after the substitution
+// z = p + (q - p)(1 - cos(pi t))/2 with Gauss-Legendre nodes in t.
+__constant__ double c_gl_t[kGlNodes], c_gl_w[kGlNodes];
+
+// area of {x >= u, y >= v} inside the disk of radius r, for u, v >= 0
+__device__ double disk_corner(double r, double u, double v)
+{
+    if (u * u + v * v >= r * r) return 0.0;
+    const double r2 = r * r, x1 = sqrt(r2 - v * v);
+    const double gu = u * sqrt(fmax(r2 - u * u, 0.0)) + r2 * asin(fmin(u / r, 1.0));
+    const double g1 = x1 * v + r2 * asin(fmin(x1 / r, 1.0));
+    return 0.5 * (g1 - gu) - v * (x1 - u);
+}
+
+// the same for any signs: a negative bound is reflected (the half-plane
+// x >= u < 0 is twice x >= 0 less x >= -u)
+__device__ double disk_quadrant(double r, double u, double v)
+{
+    if (u >= 0.0 && v >= 0.0) return disk_corner(r, u, v);
+    if (v >= 0.0) return 2.0 * disk_corner(r, 0.0, v) - disk_corner(r, -u, v);
+    if (u >= 0.0) return 2.0 * disk_corner(r, u, 0.0) - disk_corner(r, u, -v);
+    return 2.0 * (2.0 * disk_corner(r, 0.0, 0.0) - disk_corner(r, 0.0, -v)) -
+           (2.0 * disk_corner(r, -u, 0.0) - disk_corner(r, -u, -v));
+}
+
+__device__ double disk_rect(double r, double x0, double x1, double y0, double y1)
+{
+    return disk_quadrant(r, x0, y0) - disk_quadrant(r, x1, y0) - disk_quadrant(r, x0, y1) + disk_quadrant(r, x1, y1);
+}
+
+// volume of the ball (centre c, radius R) inside the box [lo, hi]
+__device__ double ball_box(const double c[3], double R, const double lo[3], const double hi[3])
+{
+    const double za = fmax(lo[2], c[2] - R), zb = fmin(hi[2], c[2] + R);
+    if (za >= zb || lo[0] >= c[0] + R || hi[0] <= c[0] - R || lo[1] >= c[1] + R || hi[1] <= c[1] - R) return 0.0;
+    const double x0 = lo[0] - c[0], x1 = hi[0] - c[0], y0 = lo[1] - c[1], y1 = hi[1] - c[1];
+    const double dist[8] = {fabs(x0), fabs(x1), fabs(y0), fabs(y1), sqrt(x0 * x0 + y0 * y0), sqrt(x1 * x1 + y0 * y0),
+                            sqrt(x0 * x0 + y1 * y1), sqrt(x1 * x1 + y1 * y1)};
+    double cut[18];
+    int nc = 0;
+    cut[nc++] = za;
+    cut[nc++] = zb;
+    for (int k = 0; k < 8; ++k) {
+        if (dist[k] >= R) continue;
+        const double h = sqrt(R * R - dist[k] * dist[k]);
+        if (c[2] - h > za && c[2] - h < zb) cut[nc++] = c[2] - h;
+        if (c[2] + h > za && c[2] + h < zb) cut[nc++] = c[2] + h;
+    }
+    for (int i = 1; i < nc; ++i)   // insertion sort of at most 18 heights
+        for (int j = i; j > 0 && cut[j] < cut[j - 1]; --j) {
+            const double t = cut[j];
+            cut[j] = cut[j - 1];
+            cut[j - 1] = t;
+        }
+    double v = 0.0;
+    for (int k = 0; k + 1 < nc; ++k) {
+        const double p = cut[k], q = cut[k + 1];
+        if (!(q > p)) continue;
+        double sum = 0.0;
+        for (int i = 0; i < kGlNodes; ++i) {
+            const double t = c_gl_t[i];
+            const double z = p + (q - p) * 0.5 * (1.0 - cospi(t));
+            const double h = z - c[2];
+            const double r2 = R * R - h * h;
+            if (r2 > 0.0) sum += c_gl_w[i] * disk_rect(sqrt(r2), x0, x1, y0, y1) * sinpi(t);
+        }
+        v += sum * (q - p) * 0.5 * kPi;
+    }
+    return v;
+}
+
+// One thread per source; pass 0 sums the in-domain volume, pass 1 deposits.
+__global__ void k_deposit_spheres(const double *__restrict__ xyz, const double *__restrict__ q,
+                                  const int32_t *__restrict__ sdom, int32_t n_src, const DomDev *__restrict__ doms,
+                                  const int4 *__restrict__ geo, const int2 *__restrict__ topo, double radius_cm,
+                                  double *ndot, int32_t *err)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_src) return;
+    const DomDev D = doms[sdom[s]];
+    const double R = radius_cm / D.dx_cm;
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = xyz[3 * s + a] / D.dx_cm;
+    if (!(q[s] >= 0.0) || !isfinite(q[s])) {
+        atomicOr(err, 1);
+        return;
+    }
+    double total = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        int stack[160];
+        int sp = 0;
+        stack[sp++] = D.root;
+        while (sp > 0) {
+            const int n = stack[--sp];
+            const int4 g = geo[n];
+            const int sz = g.w & kSizeMask;
+            const double lo[3] = {(double)g.x, (double)g.y, (double)g.z};
+            const double hi[3] = {lo[0] + sz, lo[1] + sz, lo[2] + sz};
+            bool touch = true;
+            for (int a = 0; a < 3; ++a) touch &= lo[a] < u[a] + R && hi[a] > u[a] - R;
+            if (!touch) continue;
+            const int2 tp = topo[n];
+            if (tp.y == 0) {
+                const double v = ball_box(u, R, lo, hi);
+                if (v > 0.0) {
+                    if (pass == 0) total += v;
+                    else atomicAdd(&ndot[tp.x], q[s] * (v / total));
+                }
+            } else {
+                if (sp + tp.y > 160) {
+                    atomicOr(err, 4);
+                    return;
+                }
+                for (int c = 0; c < tp.y; ++c) stack[sp++] = tp.x + c;
+            }
+        }
+        if (pass == 0 && !(total > 0.0)) {
+            atomicOr(err, 1);
+            return;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a2. Cell quantities in internal units (length: finest cell of the domain;
 // rate: rate_unit, a power of two).  s = ndot - alpha_B n^2 dV is netted
@@ -1256,6 +1384,8 @@ tr_status check_params(tr_ctx *c, const tr_params &p)
     if (!(p.theta >= 0) || !std::isfinite(p.theta)) return fail(c, TR_EINVAL, "theta must be >= 0");
     if (!std::isfinite(p.theta_if) || !std::isfinite(p.theta_src))
         return fail(c, TR_EINVAL, "theta_if and theta_src must be finite");
+    if (!(p.src_radius_cm >= 0) || !std::isfinite(p.src_radius_cm))
+        return fail(c, TR_EINVAL, "src_radius_cm must be >= 0");
     if (!(p.alpha_b >= 0) || !std::isfinite(p.alpha_b)) return fail(c, TR_EINVAL, "alpha_b must be >= 0");
     if (p.subsample < 1 || p.subsample > 4) return fail(c, TR_EINVAL, "subsample must be in [1, 4]");
     if (p.max_iter < 0) return fail(c, TR_EINVAL, "max_iter must be >= 0");
@@ -1497,6 +1627,35 @@ tr_status upload_sources(tr_ctx *c)
     return TR_OK;
 }
 
+// Gauss-Legendre nodes and weights on [0, 1] for the sphere deposit: the
+// roots of P_n by Newton's method from Tricomi's initial estimates.
+tr_status upload_gauss_legendre(tr_ctx *c)
+{
+    double t[kGlNodes], w[kGlNodes];
+    const int n = kGlNodes;
+    for (int i = 1; i <= n; ++i) {
+        double x = (1.0 - 1.0 / (8.0 * n * n) + 1.0 / (8.0 * n * n * n)) * std::cos(kPi * (4 * i - 1) / (4.0 * n + 2.0));
+        double d = 0.0;
+        for (int it = 0; it < 50; ++it) {
+            double pm = 1.0, p = x;   // P_0, P_1
+            for (int k = 2; k <= n; ++k) {
+                const double pn = ((2 * k - 1) * x * p - (k - 1) * pm) / k;
+                pm = p;
+                p = pn;
+            }
+            d = n * (pm - x * p) / (1.0 - x * x);   // P_n'
+            const double step = p / d;
+            x -= step;
+            if (std::fabs(step) < 1e-17) break;
+        }
+        t[i - 1] = 0.5 * (1.0 + x);
+        w[i - 1] = 1.0 / ((1.0 - x * x) * d * d);
+    }
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_t), t, sizeof(t)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), w, sizeof(w)));
+    return TR_OK;
+}
+
 tr_status read_flags(tr_ctx *c)
 {
     int32_t f[2] = {0, 0};
@@ -1544,6 +1703,10 @@ tr_status tr_create(tr_ctx **out, const tr_params *p, void *stream)
     // flags and counters start at zero (a sync before any launch reads them)
     if (hipMemset(c->queue, 0, 64) != hipSuccess || hipMemset(c->stats, 0, 64) != hipSuccess ||
         hipMemset(c->err_flags, 0, 64) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        tr_destroy(c);
+        return TR_EHIP;
+    }
+    if (upload_gauss_legendre(c) != TR_OK) {
         tr_destroy(c);
         return TR_EHIP;
     }
@@ -1732,8 +1895,15 @@ tr_status enqueue_build(tr_ctx *c, const double *n_h, const double *f_prev, int3
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->err_flags, (int64_t)2, 0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid1(ncell)), dim3(256), 0, c->stream, c->ndot, ncell, 0.0);
     if (c->n_src_dev > 0)
-        hipLaunchKernelGGL(k_deposit, dim3(grid1(c->n_src_dev, 64)), dim3(64), 0, c->stream, c->d_sxyz, c->d_sq,
-                           c->d_sdom, c->n_src_dev, c->doms, c->geo, c->topo_d, c->ndot, c->err_flags);
+    {
+        if (c->p.src_radius_cm > 0.0)
+            hipLaunchKernelGGL(k_deposit_spheres, dim3(grid1(c->n_src_dev, 64)), dim3(64), 0, c->stream, c->d_sxyz,
+                               c->d_sq, c->d_sdom, c->n_src_dev, c->doms, c->geo, c->topo_d, c->p.src_radius_cm,
+                               c->ndot, c->err_flags);
+        else
+            hipLaunchKernelGGL(k_deposit, dim3(grid1(c->n_src_dev, 64)), dim3(64), 0, c->stream, c->d_sxyz, c->d_sq,
+                               c->d_sdom, c->n_src_dev, c->doms, c->geo, c->topo_d, c->ndot, c->err_flags);
+    }
     hipLaunchKernelGGL(k_cell_quantities, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, n_h, c->ndot, f_prev,
                        c->cell_node, c->cell_dom, c->doms, c->geo, thin, c->mom, nn, c->err_flags);
     for (int l = c->depth_max - 2; l >= 0; --l) {

@@ -314,6 +314,22 @@ def test_long_walks_use_device_lists(T, orc):
         assert st.nodes_accepted / P.total_cells() > 2048
 
 
+@pytest.mark.parametrize("radius_cells", [0.45, 1.7])
+def test_sphere_sources(T, orc, radius_cells):
+    """Sources as uniform spheres (Sec. 2.7): the exact-volume deposit against
+    the oracle's, through thin and absorbing sweeps, uniform and AMR grids."""
+    for P in (W.small_lognormal(16, n_src=4, seed=26), W.small_amr(2, seed=27)):
+        r = radius_cells * P.domains[0].finest_dx_cm()
+        f0, i0 = orc_sweep(orc, P, thin=True, src_radius_cm=r)
+        f1, i1 = orc_sweep(orc, P, f_prev=f0, src_radius_cm=r)
+        for prec, tol in ((T.TR_FP64, TOL64), (T.TR_FP32C, TOL32)):
+            g0, j0, _ = gpu_sweep(T, P, prec, thin=True, src_radius_cm=r)
+            compare(g0, j0, f0, i0, tol, name=f"{P.name} r {radius_cells} thin prec {prec}")
+            g1, j1, _ = gpu_sweep(T, P, prec, f_prev=f0, src_radius_cm=r)
+            compare(g1, j1, f1, i1, tol, front=None if prec == T.TR_FP64 else front_mask(P, f1),
+                    name=f"{P.name} r {radius_cells} absorbing prec {prec}")
+
+
 def test_errors(T):
     P = W.small_uniform(16)
     ctx = T.context_for(P, T.TR_FP64)
