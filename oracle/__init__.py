@@ -38,7 +38,7 @@ class Params(C.Structure):
     _fields_ = [("nside", C.c_int32), ("n_radial", C.c_int32), ("eta_r", C.c_double),
                 ("theta", C.c_double), ("alpha_b", C.c_double), ("subsample", C.c_int32),
                 ("zeta_g", C.c_int32), ("theta_if", C.c_double), ("theta_src", C.c_double),
-                ("src_radius_cm", C.c_double)]
+                ("src_radius_cm", C.c_double), ("eps_kernel", C.c_int32), ("mass_kernel", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -69,6 +69,10 @@ def lib():
         L.orc_deposit.argtypes = [C.POINTER(Domain), C.c_int64, dp, dp, dp]
         L.orc_deposit_spheres.argtypes = [C.POINTER(Domain), C.c_int64, dp, dp, C.c_double, dp]
         L.orc_ball_box_volume.restype = C.c_double
+        L.orc_wg.restype = C.c_double
+        L.orc_wg.argtypes = [C.c_double]
+        L.orc_mass_weights.argtypes = [C.c_int32, C.c_int32, dp, C.c_double, C.c_double, dp]
+        L.orc_eps_weights.argtypes = [C.c_int32, C.c_int32, dp, C.c_double, C.c_double, dp]
         L.orc_ball_box_volume.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_delta_cell.restype = C.c_double
         L.orc_delta_cell.argtypes = [C.c_int64, dp, dp]
@@ -126,6 +130,8 @@ def _c_params(p, **over):
     q.theta_if = float(over.get("theta_if", getattr(p, "theta_if", 0.0)))
     q.theta_src = float(over.get("theta_src", getattr(p, "theta_src", 0.0)))
     q.src_radius_cm = float(over.get("src_radius_cm", getattr(p, "src_radius_cm", 0.0)))
+    q.eps_kernel = int(over.get("eps_kernel", getattr(p, "eps_kernel", 0)))
+    q.mass_kernel = int(over.get("mass_kernel", getattr(p, "mass_kernel", 0)))
     return q
 
 
@@ -171,6 +177,27 @@ def deposit(dom, xyz, q, radius_cm=0.0):
     else:
         _check(lib().orc_deposit(C.byref(d), len(q), _dp(xyz), _dp(q), _dp(out)), "deposit")
     return out
+
+
+K_DEFAULT, K_F1, K_F2, K_F3, K_F3N, K_P, K_G = 0, 1, 2, 3, 4, 5, 6
+
+
+def wg(x):
+    return float(lib().orc_wg(float(x)))
+
+
+def mass_weights(kind, r, d, h):
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    v = np.zeros(len(r))
+    lib().orc_mass_weights(int(kind), len(r), _dp(r), float(d), float(h), _dp(v))
+    return v
+
+
+def eps_weights(kind, r, d, h):
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    u = np.zeros(len(r))
+    lib().orc_eps_weights(int(kind), len(r), _dp(r), float(d), float(h), _dp(u))
+    return u
 
 
 def ball_box_volume(centre, radius, lo, hi):

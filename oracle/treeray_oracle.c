@@ -729,6 +729,108 @@ void orc_wf3_weights(int32_t n, const double *r, double d, double *u)
     u[i + 1] = 1.0 - u[i];
 }
 
+/* Gaussian kernel W_g (App. A.1): exp(-x^2) inside |x| < sqrt(3)/2. */
+double orc_wg(double x)
+{
+    x = fabs(x);
+    return x < 0.5 * sqrt(3.0) ? exp(-x * x) : 0.0;
+}
+
+/* Normalised smoothing-kernel weights (App. A): W_p (kind ORC_K_P) or W_g
+ * (ORC_K_G) of x = (r_i - d)/h, with the same linear fallback as W_p. */
+void orc_mass_weights(int32_t kind, int32_t n, const double *r, double d, double h, double *v)
+{
+    if (kind != ORC_K_G) {
+        orc_wp_weights(n, r, d, h, v);
+        return;
+    }
+    double sum = 0;
+    for (int i = 0; i < n; ++i) {
+        v[i] = orc_wg((r[i] - d) / h);
+        sum += v[i];
+    }
+    if (sum > 0) {
+        for (int i = 0; i < n; ++i) v[i] /= sum;
+        return;
+    }
+    for (int i = 0; i < n; ++i) v[i] = 0;
+    if (d >= r[n - 1]) { v[n - 1] = 1; return; }
+    int i = 0;
+    while (!(r[i] <= d && d < r[i + 1])) ++i;
+    v[i] = (r[i + 1] - d) / (r[i + 1] - r[i]);
+    v[i + 1] = 1.0 - v[i];
+}
+
+/* Emission weights u_i (App. A.3 and the smoothing kernels):
+ *  ORC_K_F3 (default): two-point W_f,3 (orc_wf3_weights);
+ *  ORC_K_F1: the bracket points with u_i/r_i^2 + u_{i+1}/r_{i+1}^2 = 1/d^2
+ *    and u_{i+1}/u_i = (d - r_i)/(r_{i+1} - d);
+ *  ORC_K_F2: the bracket points with the flux also exact at r_{i-1};
+ *  ORC_K_F3N: W_f,3 over the N points inside the node's extent
+ *    (|r_k - d| < sqrt(3)/2 h, k >= 1), u linear in the point index, with
+ *    sum u = 1 and sum u/r^2 = 1/d^2 (eqs. eKernFC1, eKernFC2);
+ *  ORC_K_P, ORC_K_G: the smoothing kernels.
+ * reading: F1 and F2 use the bracket and fall-backs of W_f,3; F2 needs
+ * i >= 2 (at i = 1 its two conditions coincide) and F2 and F3N fall back to
+ * the two-point W_f,3 when a weight would be negative or N < 2. */
+void orc_eps_weights(int32_t kind, int32_t n, const double *r, double d, double h, double *u)
+{
+    if (kind == ORC_K_P || kind == ORC_K_G) {
+        orc_mass_weights(kind, n, r, d, h, u);
+        return;
+    }
+    orc_wf3_weights(n, r, d, u);
+    if (kind == ORC_K_F3 || kind == ORC_K_DEFAULT) return;
+    if (kind == ORC_K_F1 || kind == ORC_K_F2) {
+        if (d >= r[n - 1] || d < r[1]) return;      /* the W_f,3 fall-backs */
+        int i = 1;
+        while (!(r[i] <= d && d < r[i + 1])) ++i;
+        double ui, un;
+        if (kind == ORC_K_F1) {
+            double rho = (d - r[i]) / (r[i + 1] - d);
+            ui = 1.0 / (d * d * (1.0 / (r[i] * r[i]) + rho / (r[i + 1] * r[i + 1])));
+            un = rho * ui;
+        } else {
+            if (i < 2) return;
+            /* a11 ui + a12 un = b1, a21 ui + a22 un = b2 */
+            double a11 = 1.0 / (r[i] * r[i]), a12 = 1.0 / (r[i + 1] * r[i + 1]), b1 = 1.0 / (d * d);
+            double p = r[i - 1];
+            double a21 = 1.0 / ((r[i] - p) * (r[i] - p)), a22 = 1.0 / ((r[i + 1] - p) * (r[i + 1] - p));
+            double b2 = 1.0 / ((d - p) * (d - p));
+            double det = a11 * a22 - a12 * a21;
+            ui = (b1 * a22 - a12 * b2) / det;
+            un = (a11 * b2 - a21 * b1) / det;
+            if (!(ui >= 0) || !(un >= 0)) return;
+        }
+        for (int k = 0; k < n; ++k) u[k] = 0;
+        u[i] = ui;
+        u[i + 1] = un;
+        return;
+    }
+    /* ORC_K_F3N */
+    int lo = -1, N = 0;
+    for (int k = 1; k < n; ++k)
+        if (fabs(r[k] - d) < 0.5 * sqrt(3.0) * h) {
+            if (lo < 0) lo = k;
+            ++N;
+        }
+    if (N < 2) return;
+    /* u_k = a + b (k - lo): sum u = 1, sum u / r^2 = 1/d^2 */
+    double s0 = 0, s1 = 0, t0 = 0, t1 = 0;
+    for (int m = 0; m < N; ++m) {
+        s0 += 1.0;
+        s1 += (double)m;
+        t0 += 1.0 / (r[lo + m] * r[lo + m]);
+        t1 += (double)m / (r[lo + m] * r[lo + m]);
+    }
+    double det = s0 * t1 - s1 * t0;
+    double a = (t1 - s1 / (d * d)) / det, b = (s0 / (d * d) - t0) / det;
+    for (int m = 0; m < N; ++m)
+        if (a + b * (double)m < 0) return;
+    for (int k = 0; k < n; ++k) u[k] = 0;
+    for (int m = 0; m < N; ++m) u[lo + m] = a + b * (double)m;
+}
+
 /* ------------------------------------------------------------------------ */
 /* On-the-Spot integration along one ray (Sec. 2.5)
  * Phi_{j,j} = eps_j / 4pi at every point holding emission; moving inwards,
@@ -925,13 +1027,13 @@ static void map_node(const walk_t *w, const onode_t *x, const cellq_t *q_overrid
     }
     double d = sqrt(d2) * g->dx;
     double h = (double)x->size * g->dx;
-    orc_wf3_weights(nr, r, d, b->u);
-    orc_wp_weights(nr, r, d, h, b->v);
+    orc_eps_weights(w->p->eps_kernel, nr, r, d, h, b->u);
+    orc_mass_weights(w->p->mass_kernel, nr, r, d, h, b->v);
     for (int k = 0; k < npl; ++k) {
         double wk = (double)b->pc[k] / (double)ns3;
         int64_t base = b->pl[k] * nr;
         for (int i = 0; i < nr; ++i) {
-            if (x->eps > 0) b->eps[base + i] += wk * x->eps * b->u[i];
+            if (x->eps > 0 && b->u[i] != 0) b->eps[base + i] += wk * x->eps * b->u[i];
             b->A[base + i] += wk * x->alpha * b->v[i];
             b->E[base + i] += wk * x->erad * b->v[i];
             b->V[base + i] += wk * x->vol * b->v[i];
@@ -973,7 +1075,7 @@ static int sweep_target(const sweep_ctx_t *S, int64_t tc, tbuf_t *b, walk_t *w, 
     /* self term */
     const cellq_t *ct = &S->cq[tc];
     double dxt = (double)g->size[tc] * g->dx;
-    orc_wp_weights(nr, S->r, 0.0, dxt, b->wp_self);
+    orc_mass_weights(S->p->mass_kernel, nr, S->r, 0.0, dxt, b->wp_self);
     for (int64_t k = 0; k < npix; ++k)
         for (int i = 0; i < nr; ++i) {
             double wv = b->wp_self[i] / (double)npix;

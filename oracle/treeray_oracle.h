@@ -35,7 +35,11 @@ typedef struct {
     double theta_if;           /* IF MAC opening angle (Sec. 2.4); <= 0: off */
     double theta_src;          /* Src MAC opening angle (Sec. 2.4); <= 0: off */
     double src_radius_cm;      /* > 0: sources are uniform spheres of this radius (Sec. 2.7) */
+    int32_t eps_kernel;        /* emission kernel, ORC_K_* (0: two-point W_f,3) */
+    int32_t mass_kernel;       /* kernel of A, E, V: ORC_K_P (0 too) or ORC_K_G */
 } orc_params;
+
+enum { ORC_K_DEFAULT = 0, ORC_K_F1 = 1, ORC_K_F2 = 2, ORC_K_F3 = 3, ORC_K_F3N = 4, ORC_K_P = 5, ORC_K_G = 6 };
 
 typedef struct {
     int64_t nodes_accepted;    /* summed over the swept targets */
@@ -82,6 +86,11 @@ int orc_deposit_spheres(const orc_domain *d, int64_t n_src, const double *src_xy
                         const double *src_q, double radius_cm, double *ndot_out);
 /* volume of the ball (centre, R) inside the box [lo, hi] */
 double orc_ball_box_volume(double cx, double cy, double cz, double R, const double *lo, const double *hi);
+
+/* radial kernels of App. A: W_g, smoothing weights (P or G), emission weights */
+double orc_wg(double x);
+void orc_mass_weights(int32_t kind, int32_t n, const double *r, double d, double h, double *v_out);
+void orc_eps_weights(int32_t kind, int32_t n, const double *r, double d, double h, double *u_out);
 
 /* OpenMP threads a sweep uses */
 int32_t orc_num_threads(void);
