@@ -88,6 +88,10 @@ typedef struct {
     double src_radius_cm;       /* > 0: sources are uniform spheres of this radius (Sec. 2.7),
                                    each cell taking the share of the rate equal to its part of
                                    the sphere's in-domain volume; 0: point sources */
+    int32_t eps_kernel;         /* radial kernel of the emission (App. A): 0 or 3 two-point
+                                   W_f,3, 1 W_f,1, 2 W_f,2, 4 W_f,3 over the N points inside the
+                                   node's extent, 5 W_p, 6 W_g */
+    int32_t mass_kernel;        /* radial kernel of A, E, V and the self term: 0 or 5 W_p, 6 W_g */
 } tr_params;
 
 typedef struct {

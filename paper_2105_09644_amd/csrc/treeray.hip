@@ -351,6 +351,8 @@ struct SweepArgs {
     float guard_tol;
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
     int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
+    int32_t eps_kernel;      // emission kernel (K_F1 .. K_G; 0 or K_F3: two-point W_f,3)
+    int32_t mass_gauss;      // 1: W_g for A, E, V and the self term; 0: W_p
     // walk lists too long for LDS: the item is queued in ovf and a second
     // launch (k_sweep_fallback) walks it with per-workgroup lists of gfmax /
     // gamax entries in device memory
@@ -380,6 +382,16 @@ __device__ inline void top_max(int *p, int v)
         __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
         *p = *p > v ? *p : v;
+}
+
+// radial kernels by kind: 5 W_p, 6 W_g (App. A.1, A.2)
+enum { K_F1 = 1, K_F2 = 2, K_F3 = 3, K_F3N = 4, K_P = 5, K_G = 6 };
+template <typename Real>
+__device__ inline Real smooth_kernel(bool gauss, Real x)
+{
+    if (!gauss) return wp_kernel<Real>(x);
+    x = x < (Real)0 ? -x : x;
+    return x < (Real)0.86602540378443864676 ? (Real)exp((double)(-x * x)) : (Real)0;
 }
 
 // Phi (photon rate per steradian) lives in the eps slot of a point once the
@@ -615,6 +627,77 @@ __device__ inline T rdlane(T v, int l)
     }
 }
 
+// W_f,1 and W_f,2 (App. A.3) on the bracket r_i <= d < r_{i+1}: both keep the
+// flux at the target exact; W_f,1 takes u_{i+1}/u_i = (d - r_i)/(r_{i+1} - d),
+// W_f,2 also makes the flux exact at r_{i-1} (i >= 2; it keeps W_f,3 when a
+// weight would be negative).  Solved in FP64.
+template <typename Real>
+__device__ void two_point_variant(int ek, const Real *rt, int i, double d, Real &u0, Real &u1)
+{
+    const double ri = (double)rt[i], rn = (double)rt[i + 1];
+    if (ek == K_F1) {
+        const double rho = (d - ri) / (rn - d);
+        const double ui = 1.0 / (d * d * (1.0 / (ri * ri) + rho / (rn * rn)));
+        u0 = (Real)ui;
+        u1 = (Real)(rho * ui);
+        return;
+    }
+    if (i < 2) return;
+    const double p = (double)rt[i - 1];
+    const double a11 = 1.0 / (ri * ri), a12 = 1.0 / (rn * rn), b1 = 1.0 / (d * d);
+    const double a21 = 1.0 / ((ri - p) * (ri - p)), a22 = 1.0 / ((rn - p) * (rn - p)), b2 = 1.0 / ((d - p) * (d - p));
+    const double det = a11 * a22 - a12 * a21;
+    const double ui = (b1 * a22 - a12 * b2) / det, un = (a11 * b2 - a21 * b1) / det;
+    if (ui >= 0.0 && un >= 0.0) {
+        u0 = (Real)ui;
+        u1 = (Real)un;
+    }
+}
+
+// N-point W_f,3 (App. A.3, eqs. eKernFC1, eKernFC2): over the points k >= 1
+// inside the node's extent, |r_k - d| < sqrt(3)/2 h, weights a + b (k - le)
+// with sum 1 and sum 1/r_k^2 = 1/d^2.  Leaves mode 0 (two-point) when fewer
+// than two points qualify or a weight would be negative.  Solved in FP64.
+template <typename Real>
+__device__ void n_point_f3(const Real *rt, int l0, int h0, double d, double h, int &mode, int &le, int &ne, Real &ea,
+                           Real &eb)
+{
+    const double half = 0.86602540378443864676 * h;
+    int first = -1, n = 0;
+    double s1 = 0, t0 = 0, t1 = 0;
+    for (int k = l0 > 1 ? l0 : 1; k <= h0; ++k) {
+        const double rk = (double)rt[k];
+        if (fabs(rk - d) >= half) continue;
+        if (first < 0) first = k;
+        const double m = (double)(k - first), w = 1.0 / (rk * rk);
+        s1 += m;
+        t0 += w;
+        t1 += m * w;
+        ++n;
+    }
+    if (n < 2) return;
+    const double det = (double)n * t1 - s1 * t0;
+    const double av = (t1 - s1 / (d * d)) / det, bv = ((double)n / (d * d) - t0) / det;
+    if (av < 0.0 || av + bv * (double)(n - 1) < 0.0) return;
+    mode = 1;
+    le = first;
+    ne = n;
+    ea = (Real)av;
+    eb = (Real)bv;
+}
+
+// Weight of support point i (offset io from the support's first point) in the
+// spread emission forms: 1 linear N-point W_f,3, 2 a smoothing kernel scaled by
+// ea, 3 the mass fall-back split (fb on the first point, 1 - fb on the next).
+template <typename Real>
+__device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, Real ea, Real eb, Real fb, Real rcoef,
+                                       Real d, Real hinv, bool gauss)
+{
+    if (mode == 1) return (i >= le && i < le + ne) ? ea + eb * (Real)(i - le) : (Real)0;
+    if (mode == 2) return smooth_kernel<Real>(gauss, (rcoef * (Real)(i * i) - d) * hinv) * ea;
+    return io == 0 ? fb : (Real)1 - fb;
+}
+
 // Maps the accepted nodes acc[0..cnt) (cnt <= 64) onto the target's rays;
 // executed by a whole wave in two phases.
 //  Phase 1, lane = node: loads the node, its mass-centre distance d, the
@@ -625,7 +708,8 @@ __device__ inline T rdlane(T v, int l)
 //   in k over s^3), then the scatter, with lanes covering (pixel, point) pairs.
 // The evaluation points are r_i = c i^2; the per-node loop recomputes them
 // in registers, so it makes no memory round trip besides its atomics.
-template <typename Real, bool ATOMIC>
+// KV: the radial-kernel variants of App. A (otherwise two-point W_f,3 and W_p)
+template <typename Real, bool ATOMIC, bool KV>
 __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *rt, int nr, Real rc_inv, Real rcoef,
                           const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
 {
@@ -635,6 +719,11 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
     // ---------------- phase 1 ----------------
     int bx = 0, by = 0, bz = 0, ex = 1, ey = 1, ez = 1, lo = 0, nsup = 0, ie = 1;
     Real d = 1, hinv = 1, wscale = 0, fb0 = 1, qa = 0, qe = 0, qv = 0, e0 = 0, e1 = 0;
+    // emission spread over several points: mode 1 linear (a + b (i - le) on [le, le + ne)),
+    // 2 a smoothing kernel scaled by ea, 3 the mass fall-back weights; etop: outermost point
+    int emode = 0, le = 0, ne = 0, etop = 1;
+    Real ea = 0, eb = 0, qeps = 0;
+    const bool mg = KV && a.mass_gauss != 0;
     if (lane < cnt) {
         const int n = acc[lane];
         const int4 g = a.geo[n];
@@ -659,7 +748,7 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
         l0 = l0 < 0 ? 0 : l0;
         h0 = h0 > nr - 1 ? nr - 1 : h0;
         Real sum = 0;
-        for (int i = l0; i <= h0; ++i) sum += wp_kernel<Real>((rcoef * (Real)(i * i) - d) * hinv);
+        for (int i = l0; i <= h0; ++i) sum += smooth_kernel<Real>(mg, (rcoef * (Real)(i * i) - d) * hinv);
         if (sum > (Real)0) {
             wscale = frcp(sum);
             lo = l0;
@@ -677,7 +766,23 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
             nsup = 2;
             fb0 = (rt[ib + 1] - d) * frcp(rt[ib + 1] - rt[ib]);
         }
-        if (A.w > (Real)0) {   // W_f,3 bracket r_i <= d < r_{i+1}, i >= 1
+        qeps = A.w;
+        const int ek = KV ? a.eps_kernel : 0;
+        if (A.w > (Real)0 && (ek == K_P || ek == K_G)) {   // a smoothing kernel for the emission too
+            if (sum > (Real)0) {
+                Real es = 0;
+                for (int i = l0; i <= h0; ++i) {
+                    const Real v = smooth_kernel<Real>(ek == K_G, (rcoef * (Real)(i * i) - d) * hinv);
+                    es += v;
+                    if (v > (Real)0) etop = i;
+                }
+                emode = 2;
+                ea = frcp(es);
+            } else {
+                emode = 3;
+                etop = lo + nsup - 1;
+            }
+        } else if (A.w > (Real)0) {   // W_f,3 bracket r_i <= d < r_{i+1}, i >= 1
             Real u0 = 1, u1 = 0;
             if (d >= rt[nr - 1]) {
                 ie = nr - 1;
@@ -690,9 +795,18 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
                 const Real ai = frcp(rt[ie] * rt[ie]), an = frcp(rt[ie + 1] * rt[ie + 1]), ad = frcp(d * d);
                 u0 = (ad - an) * frcp(ai - an);
                 u1 = (Real)1 - u0;
+                if (ek == K_F1 || ek == K_F2)
+                    two_point_variant(ek, rt, ie, (double)d, u0, u1);
             }
-            e0 = A.w * u0;
-            e1 = A.w * u1;
+            if (ek == K_F3N && sum > (Real)0)
+                n_point_f3(rt, l0, h0, (double)d, (double)h, emode, le, ne, ea, eb);
+            if (emode == 1) {
+                etop = le + ne - 1;
+            } else {
+                e0 = A.w * u0;
+                e1 = A.w * u1;
+                etop = u1 != (Real)0 ? ie + 1 : ie;
+            }
         }
     }
 
@@ -708,6 +822,7 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
     const Real inv_s3 = (Real)1 / (Real)s3;
     const uint64_t act_mask = __ballot(active);
     const int packed = lo | (nsup << 8) | (ie << 16);   // each below 256
+    const int epacked = emode | (le << 2) | (ne << 10) | (etop << 18);   // 2 + 8 + 8 + 8 bits
     // per node (lane = node): sub-box origin relative to the target and sub-box steps, FP32
     const float ox = 0.5f * (float)(2 * bx - tx), oy = 0.5f * (float)(2 * by - ty), oz = 0.5f * (float)(2 * bz - tz);
     const float sx = (float)ex * inv_s, sy = (float)ey * inv_s, sz = (float)ez * inv_s;
@@ -741,25 +856,31 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
         const Real jd = rdlane(d, j), jhinv = rdlane(hinv, j), jws = rdlane(wscale, j), jfb = rdlane(fb0, j);
         const Real ja = rdlane(qa, j), je = rdlane(qe, j), jv = rdlane(qv, j);
         const Real je0 = rdlane(e0, j), je1 = rdlane(e1, j);
-        const bool has_eps = je0 != (Real)0 || je1 != (Real)0;
+        const int jep = KV ? rdlane(epacked, j) : 0;
+        const int jemode = jep & 3, jle = (jep >> 2) & 255, jne = (jep >> 10) & 255;
+        const int jetop = KV ? (jep >> 18) : (je1 != (Real)0 ? jie + 1 : jie);
+        const bool has_eps = je0 != (Real)0 || je1 != (Real)0 || jemode != 0;
         const int span = jn < 64 ? jn : 64;                         // points per batch slot
         const int G = 64 / span;                                    // pixels per batch
         // lane / span: (lane + 1/2)/span is at least 1/128 away from an integer
         const int po = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)span));
         const int io = lane - po * span;
         const bool lane_ok = po < G;
-        Real wa = 0, we = 0, wv = 0;
+        Real wa = 0, we = 0, wv = 0, wq = 0;   // wq: emission spread over the support (modes 1-3)
         if (lane_ok) {
             Real w;
             if (jws > (Real)0) {
                 const int i = jlo + io;
-                w = wp_kernel<Real>((rcoef * (Real)(i * i) - jd) * jhinv) * jws;
+                w = smooth_kernel<Real>(mg, (rcoef * (Real)(i * i) - jd) * jhinv) * jws;
             } else {
                 w = io == 0 ? jfb : (Real)1 - jfb;
             }
             wa = w * ja;
             we = w * je;
             wv = w * jv;
+            if (KV && jemode != 0) wq = emission_weight<Real>(jemode, jlo + io, io, jle, jne, rdlane(ea, j), rdlane(eb, j),
+                                                       jfb, rcoef, jd, jhinv, a.eps_kernel == K_G) *
+                                  rdlane(qeps, j);
         }
         const int col = Q_A * nrm + jlo + io;
         // --- distinct pixels: slot q (lane q of slot_k / slot_c) holds pixel k_q and its count ---
@@ -777,12 +898,15 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
             ++nd;
         }
         // emission: lane q deposits pixel q's share on the two bracket points
+        // (the spread forms go with A, E, V below); the ray's outermost emitting point
         if (has_eps && lane < nd) {
-            const Real wk = (Real)slot_c * inv_s3;
-            Real *row = buf + (size_t)slot_k * a.stride_k + Q_EPS * nrm + jie;
-            if (je0 != (Real)0) buf_add<Real, ATOMIC>(row, wk * je0);
-            if (je1 != (Real)0) buf_add<Real, ATOMIC>(row + 1, wk * je1);
-            top_max<ATOMIC>(top + slot_k, je1 != (Real)0 ? jie + 1 : jie);
+            if (jemode == 0) {
+                const Real wk = (Real)slot_c * inv_s3;
+                Real *row = buf + (size_t)slot_k * a.stride_k + Q_EPS * nrm + jie;
+                if (je0 != (Real)0) buf_add<Real, ATOMIC>(row, wk * je0);
+                if (je1 != (Real)0) buf_add<Real, ATOMIC>(row + 1, wk * je1);
+            }
+            top_max<ATOMIC>(top + slot_k, jetop);
         }
         // A, E, V: lanes cover (pixel slot, point) pairs, G slots at a time
         for (int b0 = 0; b0 < nd; b0 += G) {
@@ -794,6 +918,7 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
                 buf_add<Real, ATOMIC>(row, wk * wa);
                 buf_add<Real, ATOMIC>(row + nrm, wk * we);
                 buf_add<Real, ATOMIC>(row + 2 * nrm, wk * wv);
+                if (KV && wq != (Real)0) buf_add<Real, ATOMIC>(row - nrm, wk * wq);   // the emission row
             }
         }
         if (jn > 64) {
@@ -804,10 +929,17 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
                 Real *row = buf + (size_t)k * a.stride_k + Q_A * nrm + jlo;
                 for (int i2 = 64 + lane; i2 < jn; i2 += 64) {
                     const int i = jlo + i2;
-                    const Real w2 = jws > (Real)0 ? wp_kernel<Real>((rcoef * (Real)(i * i) - jd) * jhinv) * jws : (Real)0;
+                    const Real w2 =
+                        jws > (Real)0 ? smooth_kernel<Real>(mg, (rcoef * (Real)(i * i) - jd) * jhinv) * jws : (Real)0;
                     buf_add<Real, ATOMIC>(row + i2, wk * w2 * ja);
                     buf_add<Real, ATOMIC>(row + nrm + i2, wk * w2 * je);
                     buf_add<Real, ATOMIC>(row + 2 * nrm + i2, wk * w2 * jv);
+                    if (KV && jemode != 0) {
+                        const Real q2 = emission_weight<Real>(jemode, i, i2, jle, jne, rdlane(ea, j), rdlane(eb, j), jfb,
+                                                              rcoef, jd, jhinv, a.eps_kernel == K_G) *
+                                        rdlane(qeps, j);
+                        if (q2 != (Real)0) buf_add<Real, ATOMIC>(row - nrm + i2, wk * q2);
+                    }
                 }
             }
         }
@@ -897,7 +1029,7 @@ __device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz
 
 // The sweep of one launch.  FALLBACK: the second pass over the items whose
 // walk lists did not fit in LDS, with the lists in device memory.
-template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK>
+template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK, bool KV>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     using R4 = typename R4T<Real>::T;
@@ -1002,8 +1134,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         __syncthreads();
         if (wave == 0) {
             Real w0 = 0, w1 = 0;
-            if (lane < nr) w0 = wp_kernel<Real>(rt[lane] / (Real)tsize);
-            if (lane + 64 < nr) w1 = wp_kernel<Real>(rt[lane + 64] / (Real)tsize);
+            if (lane < nr) w0 = smooth_kernel<Real>(KV && a.mass_gauss != 0, rt[lane] / (Real)tsize);
+            if (lane + 64 < nr) w1 = smooth_kernel<Real>(KV && a.mass_gauss != 0, rt[lane + 64] / (Real)tsize);
             const Real sum = wave_sum(w0 + w1);
             if (lane < nr) wself[lane] = w0 / sum;
             if (lane + 64 < nr) wself[lane + 64] = w1 / sum;
@@ -1058,7 +1190,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             }
             end = uniform(end);
             if (end <= start) break;
-            map_nodes<Real, ATOMIC>(a, buf, top, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz, n_guard);
+            map_nodes<Real, ATOMIC, KV>(a, buf, top, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
+                                        n_guard);
         }
         __syncthreads();
         if (sc[S_OVF]) {
@@ -1136,13 +1269,26 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 template <typename Real, int WAVES, bool LDSBUF>
 __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep(SweepArgs a)
 {
-    sweep_body<Real, WAVES, LDSBUF, false>(a);
+    sweep_body<Real, WAVES, LDSBUF, false, false>(a);
 }
 
 template <typename Real, int WAVES, bool LDSBUF>
 __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_fallback(SweepArgs a)
 {
-    sweep_body<Real, WAVES, LDSBUF, true>(a);
+    sweep_body<Real, WAVES, LDSBUF, true, false>(a);
+}
+
+// the same with the radial-kernel variants (fewer launch shapes)
+template <typename Real, int WAVES, bool LDSBUF>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_kv(SweepArgs a)
+{
+    sweep_body<Real, WAVES, LDSBUF, false, true>(a);
+}
+
+template <typename Real, int WAVES, bool LDSBUF>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_kv_fallback(SweepArgs a)
+{
+    sweep_body<Real, WAVES, LDSBUF, true, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1386,6 +1532,9 @@ tr_status check_params(tr_ctx *c, const tr_params &p)
         return fail(c, TR_EINVAL, "theta_if and theta_src must be finite");
     if (!(p.src_radius_cm >= 0) || !std::isfinite(p.src_radius_cm))
         return fail(c, TR_EINVAL, "src_radius_cm must be >= 0");
+    if (p.eps_kernel < 0 || p.eps_kernel > 6) return fail(c, TR_EINVAL, "eps_kernel must be in [0, 6]");
+    if (p.mass_kernel != 0 && p.mass_kernel != 5 && p.mass_kernel != 6)
+        return fail(c, TR_EINVAL, "mass_kernel must be 0, 5 (W_p) or 6 (W_g)");
     if (!(p.alpha_b >= 0) || !std::isfinite(p.alpha_b)) return fail(c, TR_EINVAL, "alpha_b must be >= 0");
     if (p.subsample < 1 || p.subsample > 4) return fail(c, TR_EINVAL, "subsample must be in [1, 4]");
     if (p.max_iter < 0) return fail(c, TR_EINVAL, "max_iter must be >= 0");
@@ -1431,6 +1580,20 @@ constexpr size_t kLdsMax = 160 * 1024;
 using KernelFn = void (*)(SweepArgs);
 
 template <typename Real>
+KernelFn pick_kernel_kv(int waves, bool ldsbuf, bool fallback)
+{
+    if (waves == 4) {
+        if (fallback) return ldsbuf ? (KernelFn)k_sweep_kv_fallback<Real, 4, true> : (KernelFn)k_sweep_kv_fallback<Real, 4, false>;
+        return ldsbuf ? (KernelFn)k_sweep_kv<Real, 4, true> : (KernelFn)k_sweep_kv<Real, 4, false>;
+    }
+    if (waves == 8) {
+        if (fallback) return ldsbuf ? (KernelFn)k_sweep_kv_fallback<Real, 8, true> : (KernelFn)k_sweep_kv_fallback<Real, 8, false>;
+        return ldsbuf ? (KernelFn)k_sweep_kv<Real, 8, true> : (KernelFn)k_sweep_kv<Real, 8, false>;
+    }
+    return nullptr;
+}
+
+template <typename Real>
 KernelFn pick_kernel(int waves, bool ldsbuf, bool fallback)
 {
 #define TR_CASE(W)                                                                                      \
@@ -1470,6 +1633,9 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
         waves = c->tuned_waves[f32 ? 1 : 0];
         if (waves <= 0) waves = npix >= 192 ? 8 : 4;
     }
+    // the radial-kernel variants are built for 4 and 8 waves per target only
+    const bool kv = !((c->p.eps_kernel == 0 || c->p.eps_kernel == 3) && (c->p.mass_kernel == 0 || c->p.mass_kernel == 5));
+    if (kv) waves = waves <= 4 ? 4 : 8;
     L.waves = waves;
     // per-level frontier and per-target accepted-node capacities (overflow is reported)
     L.fmax = 512;
@@ -1483,8 +1649,13 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
         L.amax = 4096;
     }
     L.lds = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, L.amax, waves, L.ldsbuf);
-    L.fn = f32 ? pick_kernel<float>(waves, L.ldsbuf, false) : pick_kernel<double>(waves, L.ldsbuf, false);
-    L.fn_fb = f32 ? pick_kernel<float>(waves, L.ldsbuf, true) : pick_kernel<double>(waves, L.ldsbuf, true);
+    if (kv) {
+        L.fn = f32 ? pick_kernel_kv<float>(waves, L.ldsbuf, false) : pick_kernel_kv<double>(waves, L.ldsbuf, false);
+        L.fn_fb = f32 ? pick_kernel_kv<float>(waves, L.ldsbuf, true) : pick_kernel_kv<double>(waves, L.ldsbuf, true);
+    } else {
+        L.fn = f32 ? pick_kernel<float>(waves, L.ldsbuf, false) : pick_kernel<double>(waves, L.ldsbuf, false);
+        L.fn_fb = f32 ? pick_kernel<float>(waves, L.ldsbuf, true) : pick_kernel<double>(waves, L.ldsbuf, true);
+    }
     if (!L.fn || !L.fn_fb) return fail(c, TR_EINVAL, "waves per target must be 1, 2, 4, 8 or 16");
     HIPCHK(hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
     HIPCHK(hipFuncSetAttribute((const void *)L.fn_fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
@@ -1566,6 +1737,8 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.stride_k = L.stride_k;
     a.zeta_g = c->p.zeta_g;
     a.int_wave = L.intw ? 1 : 0;
+    a.eps_kernel = c->p.eps_kernel;
+    a.mass_gauss = c->p.mass_kernel == 6 ? 1 : 0;
     a.ovf = c->ovf;
     a.ovf_cap = c->ovf_cap;
     a.glist = c->glist;

@@ -330,6 +330,22 @@ def test_sphere_sources(T, orc, radius_cells):
                     name=f"{P.name} r {radius_cells} absorbing prec {prec}")
 
 
+@pytest.mark.parametrize("eps_kernel,mass_kernel", [(1, 0), (2, 0), (4, 0), (5, 0), (6, 6), (3, 6)])
+def test_radial_kernel_variants(T, orc, eps_kernel, mass_kernel):
+    """Radial kernels of App. A (W_f,1, W_f,2, N-point W_f,3, W_p and W_g for the
+    emission; W_g for A, E, V) against the oracle."""
+    P = W.small_lognormal(16, n_src=3, seed=32, nside=2)
+    over = dict(eps_kernel=eps_kernel, mass_kernel=mass_kernel)
+    f0, i0 = orc_sweep(orc, P, thin=True, **over)
+    f1, i1 = orc_sweep(orc, P, f_prev=f0, **over)
+    for prec, tol in ((T.TR_FP64, TOL64), (T.TR_FP32C, TOL32)):
+        g0, j0, _ = gpu_sweep(T, P, prec, thin=True, **over)
+        compare(g0, j0, f0, i0, tol, name=f"kernels {eps_kernel}/{mass_kernel} thin prec {prec}")
+        g1, j1, _ = gpu_sweep(T, P, prec, f_prev=f0, **over)
+        compare(g1, j1, f1, i1, tol, front=None if prec == T.TR_FP64 else front_mask(P, f1),
+                name=f"kernels {eps_kernel}/{mass_kernel} absorbing prec {prec}")
+
+
 def test_errors(T):
     P = W.small_uniform(16)
     ctx = T.context_for(P, T.TR_FP64)
