@@ -335,6 +335,19 @@ def two_source_cloud(n: int = 128, nside: int = 2, theta: float = 0.5, theta_if:
     return Problem(f"two_source_cloud{n}", [dom], [nh], [xyz], [np.array([3.2e48, 3.2e48])], p)
 
 
+def two_source_pair(n: int = 128, sep_pc: float = 0.4, nside: int = 2, theta: float = 0.5) -> Problem:
+    """The kernel-comparison variant of the two-source set-up (App. A): the
+    same domain filled with rarefied gas only (1e-24 g/cm^3), sources of
+    3.2e48 photons/s at (-sep, 0, 0) and (0, -sep, 0) pc."""
+    dom = uniform_domain(n, box_pc=6.0)
+    origin = (-2.0, -2.0, -3.0)
+    nh = np.full(dom.n_cells(), hydrogen_density(1e-24))
+    src_pc = np.array([[-sep_pc, 0.0, 0.0], [0.0, -sep_pc, 0.0]])
+    xyz = (src_pc - np.array(origin)) * PC_CM
+    p = Params(nside=nside, n_radial=0, eta_r=2.0, theta=theta)
+    return Problem(f"two_source_pair{n}", [dom], [nh], [xyz], [np.array([3.2e48, 3.2e48])], p)
+
+
 def rabbit_hole(width_pc: float, n_long: int = 384, axis: int = 0, nside: int = 4, theta: float = 0.25,
                 theta_if: float = 0.0, theta_src: float = 0.0) -> Problem:
     """Rabbit hole (Sec. 3.2.1): a 6 x 2 x 2 pc box of cold dense gas
