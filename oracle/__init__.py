@@ -38,7 +38,8 @@ class Params(C.Structure):
     _fields_ = [("nside", C.c_int32), ("n_radial", C.c_int32), ("eta_r", C.c_double),
                 ("theta", C.c_double), ("alpha_b", C.c_double), ("subsample", C.c_int32),
                 ("zeta_g", C.c_int32), ("theta_if", C.c_double), ("theta_src", C.c_double),
-                ("src_radius_cm", C.c_double), ("eps_kernel", C.c_int32), ("mass_kernel", C.c_int32)]
+                ("src_radius_cm", C.c_double), ("eps_kernel", C.c_int32), ("mass_kernel", C.c_int32),
+                ("periodic", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -132,6 +133,7 @@ def _c_params(p, **over):
     q.src_radius_cm = float(over.get("src_radius_cm", getattr(p, "src_radius_cm", 0.0)))
     q.eps_kernel = int(over.get("eps_kernel", getattr(p, "eps_kernel", 0)))
     q.mass_kernel = int(over.get("mass_kernel", getattr(p, "mass_kernel", 0)))
+    q.periodic = int(bool(over.get("periodic", getattr(p, "periodic", False))))
     return q
 
 

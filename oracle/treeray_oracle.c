@@ -938,6 +938,21 @@ static double opening_angle2(const orc_params *p, const onode_t *x)
     return t2;
 }
 
+/* Periodic boundaries (Sec. 2.8): a node is used through its periodic copy
+ * closest to the target.  The copy is chosen by the node's geometric centre:
+ * per axis the shift k L (L the domain's extent) puts the centre's offset
+ * from the target into (-L/2, L/2].  Isolated boundaries: no shift. */
+static void nearest_copy(const walk_t *w, const onode_t *x, double shift[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        shift[a] = 0.0;
+        if (!w->p->periodic) continue;
+        double L = (double)w->g->ext[a];
+        double off = (double)x->lo[a] + 0.5 * (double)x->size - w->xt[a];
+        shift[a] = floor((0.5 * L - off) / L) * L;
+    }
+}
+
 static int walk_node(walk_t *w, int64_t id)
 {
     const onode_t *x = &w->t->n[id];
@@ -952,9 +967,10 @@ static int walk_node(walk_t *w, int64_t id)
     } else if (x->cell >= 0) {
         open = 0;
     } else {
-        double d2 = 0;
+        double d2 = 0, sh[3];
+        nearest_copy(w, x, sh);
         for (int a = 0; a < 3; ++a) {
-            double gc = (double)x->lo[a] + 0.5 * (double)x->size - w->xt[a];
+            double gc = (double)x->lo[a] + 0.5 * (double)x->size + sh[a] - w->xt[a];
             d2 += gc * gc;
         }
         double h = (double)x->size;
@@ -1001,6 +1017,8 @@ static void map_node(const walk_t *w, const onode_t *x, const cellq_t *q_overrid
     const grid_t *g = w->g;
     int s = w->p->subsample;
     int ns3 = s * s * s;
+    double sh[3];
+    nearest_copy(w, x, sh);
     /* angular weights */
     int npl = 0;
     for (int ia = 0; ia < s; ++ia)
@@ -1010,7 +1028,7 @@ static void map_node(const walk_t *w, const onode_t *x, const cellq_t *q_overrid
                 double v[3];
                 for (int a = 0; a < 3; ++a) {
                     double ext = (double)(x->ohi[a] - x->olo[a]);
-                    double pa = (double)x->olo[a] + (((double)ii[a] + 0.5) + JIT[a]) * (ext / (double)s);
+                    double pa = (double)(x->olo[a] + sh[a]) + (((double)ii[a] + 0.5) + JIT[a]) * (ext / (double)s);
                     v[a] = pa - w->xt[a];
                 }
                 int64_t pix = orc_ang2pix(w->p->nside, v[0], v[1], v[2]);
@@ -1022,7 +1040,7 @@ static void map_node(const walk_t *w, const onode_t *x, const cellq_t *q_overrid
     /* radial weights */
     double d2 = 0;
     for (int a = 0; a < 3; ++a) {
-        double da = x->com[a] - w->xt[a];
+        double da = x->com[a] + sh[a] - w->xt[a];
         d2 += da * da;
     }
     double d = sqrt(d2) * g->dx;

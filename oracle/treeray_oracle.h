@@ -37,6 +37,7 @@ typedef struct {
     double src_radius_cm;      /* > 0: sources are uniform spheres of this radius (Sec. 2.7) */
     int32_t eps_kernel;        /* emission kernel, ORC_K_* (0: two-point W_f,3) */
     int32_t mass_kernel;       /* kernel of A, E, V: ORC_K_P (0 too) or ORC_K_G */
+    int32_t periodic;          /* 1: periodic boundaries, nearest copy of every node (Sec. 2.8) */
 } orc_params;
 
 enum { ORC_K_DEFAULT = 0, ORC_K_F1 = 1, ORC_K_F2 = 2, ORC_K_F3 = 3, ORC_K_F3N = 4, ORC_K_P = 5, ORC_K_G = 6 };

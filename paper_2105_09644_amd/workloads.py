@@ -74,6 +74,7 @@ class Params:
     src_radius_cm: float = 0.0   # > 0: sources are uniform spheres of this radius
     eps_kernel: int = 0       # emission kernel: 0 two-point W_f,3, 1 W_f,1, 2 W_f,2, 3 W_f,3, 4 N-point W_f,3, 5 W_p, 6 W_g
     mass_kernel: int = 0      # kernel of A, E, V: 0 or 5 W_p, 6 W_g
+    periodic: bool = False    # periodic boundaries (nearest copy of every node)
 
 
 @dataclass
