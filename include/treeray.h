@@ -92,6 +92,9 @@ typedef struct {
                                    W_f,3, 1 W_f,1, 2 W_f,2, 4 W_f,3 over the N points inside the
                                    node's extent, 5 W_p, 6 W_g */
     int32_t mass_kernel;        /* radial kernel of A, E, V and the self term: 0 or 5 W_p, 6 W_g */
+    int32_t periodic;           /* 1: periodic boundaries (Sec. 2.8): every node is used through
+                                   its periodic copy closest to the target (by its cube's centre);
+                                   0: isolated */
 } tr_params;
 
 typedef struct {

@@ -40,7 +40,7 @@ class _Params(C.Structure):
                 ("alpha_b", C.c_double), ("hnu_erg", C.c_double), ("eps_lim", C.c_double),
                 ("subsample", C.c_int32), ("max_iter", C.c_int32), ("zeta_g", C.c_int32), ("precision", C.c_int32),
                 ("theta_if", C.c_double), ("theta_src", C.c_double), ("src_radius_cm", C.c_double),
-                ("eps_kernel", C.c_int32), ("mass_kernel", C.c_int32)]
+                ("eps_kernel", C.c_int32), ("mass_kernel", C.c_int32), ("periodic", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -127,6 +127,7 @@ class Context:
         p.src_radius_cm = float(getattr(params, "src_radius_cm", 0.0))
         p.eps_kernel = int(getattr(params, "eps_kernel", 0))
         p.mass_kernel = int(getattr(params, "mass_kernel", 0))
+        p.periodic = int(bool(getattr(params, "periodic", False)))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         self._check(self.L.tr_create(C.byref(h), C.byref(p), C.c_void_p(self.stream.cuda_stream)), None)

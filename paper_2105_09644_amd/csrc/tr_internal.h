@@ -58,7 +58,7 @@ struct DomDev {
     int32_t r_off;         // offset into the radial tables
     int32_t cell_off;      // first global cell
     int32_t n_cells;
-    int32_t pad0;
+    int32_t ext[3];        // extent in finest cells (the period of periodic boundaries)
     double dx_cm;          // finest cell size
     double flux_unit;      // internal flux -> photons cm^-2 s^-1
     double rate_unit;      // internal rate -> photons s^-1

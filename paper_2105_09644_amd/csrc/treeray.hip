@@ -352,6 +352,7 @@ struct SweepArgs {
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
     int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
     int32_t eps_kernel;      // emission kernel (K_F1 .. K_G; 0 or K_F3: two-point W_f,3)
+    int32_t periodic;        // 1: every node through its periodic copy closest to the target
     int32_t mass_gauss;      // 1: W_g for A, E, V and the self term; 0: W_p
     // walk lists too long for LDS: the item is queued in ovf and a second
     // launch (k_sweep_fallback) walks it with per-workgroup lists of gfmax /
@@ -372,6 +373,16 @@ __device__ inline void buf_add(Real *p, Real v)
         __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
         *p += v;
+}
+
+// Periodic boundaries (Sec. 2.8): v is twice a node centre's offset from the
+// target along an axis with period L finest cells; returns the multiple of L
+// (in finest cells) that moves the offset into (-L/2, L/2], the closest copy.
+__device__ inline int nearest_copy_shift(int v, int L)
+{
+    const int num = L - v, den = 2 * L;
+    const int k = num >= 0 ? num / den : -((-num + den - 1) / den);   // floor(num / den)
+    return k * L;
 }
 
 // outermost emitting point of a ray
@@ -710,8 +721,8 @@ __device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, 
 // in registers, so it makes no memory round trip besides its atomics.
 // KV: the radial-kernel variants of App. A (otherwise two-point W_f,3 and W_p)
 template <typename Real, bool ATOMIC, bool KV>
-__device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *rt, int nr, Real rc_inv, Real rcoef,
-                          const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
+__device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *per, const Real *rt, int nr, Real rc_inv,
+                          Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
 {
     using R4 = typename R4T<Real>::T;
     const int lane = lane_id();
@@ -738,7 +749,17 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const Real *r
         const R4 A = ((const R4 *)a.pA)[n];
         const R4 B = ((const R4 *)a.pB)[n];
         qa = B.x; qe = B.y; qv = B.z;
-        const Real dxc = A.x - (Real)0.5 * (Real)tx, dyc = A.y - (Real)0.5 * (Real)ty, dzc = A.z - (Real)0.5 * (Real)tz;
+        int shx = 0, shy = 0, shz = 0;   // periodic copy closest to the target (by the cube's centre)
+        if (per) {
+            shx = nearest_copy_shift(2 * g.x + size - tx, per[0]);
+            shy = nearest_copy_shift(2 * g.y + size - ty, per[1]);
+            shz = nearest_copy_shift(2 * g.z + size - tz, per[2]);
+            bx += shx;
+            by += shy;
+            bz += shz;
+        }
+        const Real dxc = (A.x + (Real)shx) - (Real)0.5 * (Real)tx, dyc = (A.y + (Real)shy) - (Real)0.5 * (Real)ty,
+                   dzc = (A.z + (Real)shz) - (Real)0.5 * (Real)tz;
         d = fsqrt(dxc * dxc + dyc * dyc + dzc * dzc);
         const Real h = (Real)size;
         hinv = frcp(h);   // a power of two: exact
@@ -958,8 +979,8 @@ __device__ inline void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATO
 // the other waves map them while the walk goes on.
 enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_COUNT = 16 };
 
-__device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz, int *fr0, int *fr1, int *acc, int *sc,
-                            int fmax, int amax, double &n_test)
+__device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx, int ty, int tz, int *fr0, int *fr1,
+                            int *acc, int *sc, int fmax, int amax, double &n_test)
 {
     const int lane = lane_id();
     int *cur = fr0, *nxt = fr1;
@@ -987,8 +1008,13 @@ __device__ void walk_target(const SweepArgs &a, int root, int tx, int ty, int tz
                 } else if (leaf) {
                     acc_it = true;
                 } else {
-                    const double ddx = (double)(2 * g.x + sz - tx), ddy = (double)(2 * g.y + sz - ty),
-                                 ddz = (double)(2 * g.z + sz - tz);
+                    int vx = 2 * g.x + sz - tx, vy = 2 * g.y + sz - ty, vz = 2 * g.z + sz - tz;
+                    if (per) {
+                        vx += 2 * nearest_copy_shift(vx, per[0]);
+                        vy += 2 * nearest_copy_shift(vy, per[1]);
+                        vz += 2 * nearest_copy_shift(vz, per[2]);
+                    }
+                    const double ddx = (double)vx, ddy = (double)vy, ddz = (double)vz;
                     const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;
                     double th2 = a.theta2;   // lowered by the IF and Src MACs (Sec. 2.4)
                     if ((g.w & kIfBit) && a.theta_if2 > 0.0) th2 = fmin(th2, a.theta_if2);
@@ -1169,7 +1195,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         __syncthreads();
 
         // --- wave 0 walks; every wave (wave 0 once its walk is done) maps ---
-        if (wave == 0) walk_target(a, D.root, tx, ty, tz, fr0, fr1, acc, sc, fmax, amax, n_test);
+        const int *per = a.periodic ? D.ext : nullptr;
+        if (wave == 0) walk_target(a, D.root, per, tx, ty, tz, fr0, fr1, acc, sc, fmax, amax, n_test);
         for (;;) {
             int start = 0;
             if (lane == 0) start = atomicAdd(&sc[S_CLAIM], CHUNK);
@@ -1190,7 +1217,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             }
             end = uniform(end);
             if (end <= start) break;
-            map_nodes<Real, ATOMIC, KV>(a, buf, top, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
+            map_nodes<Real, ATOMIC, KV>(a, buf, top, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
                                         n_guard);
         }
         __syncthreads();
@@ -1738,6 +1765,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.zeta_g = c->p.zeta_g;
     a.int_wave = L.intw ? 1 : 0;
     a.eps_kernel = c->p.eps_kernel;
+    a.periodic = c->p.periodic ? 1 : 0;
     a.mass_gauss = c->p.mass_kernel == 6 ? 1 : 0;
     a.ovf = c->ovf;
     a.ovf_cap = c->ovf_cap;
@@ -1992,6 +2020,7 @@ tr_status tr_set_domains(tr_ctx *c, int32_t n_domains, const tr_domain *doms)
         D.cell_off = (int32_t)cbase;
         D.n_cells = (int32_t)t.n_cells;
         D.dx_cm = t.dx_cm;
+        for (int q = 0; q < 3; ++q) D.ext[q] = t.ext[q];
         D.rate_unit = 1.0;
         D.flux_unit = 1.0 / (t.dx_cm * t.dx_cm);
         D.alpha_int = c->p.alpha_b * t.dx_cm * t.dx_cm * t.dx_cm;

@@ -346,6 +346,22 @@ def test_radial_kernel_variants(T, orc, eps_kernel, mass_kernel):
                 name=f"kernels {eps_kernel}/{mass_kernel} absorbing prec {prec}")
 
 
+@pytest.mark.parametrize("make", [lambda: W.small_lognormal(16, n_src=3, seed=43),
+                                  lambda: W.small_lognormal(24, n_src=2, seed=44, nside=1),
+                                  lambda: W.rabbit_hole(0.5, 48, 2, nside=2)], ids=["cube16", "padded24", "slab48"])
+def test_periodic_boundaries(T, orc, make):
+    """Periodic boundaries (Sec. 2.8, nearest copy of every node) against the oracle."""
+    P = make()
+    f0, i0 = orc_sweep(orc, P, thin=True, periodic=True)
+    f1, i1 = orc_sweep(orc, P, f_prev=f0, periodic=True)
+    for prec, tol in ((T.TR_FP64, TOL64), (T.TR_FP32C, TOL32)):
+        g0, j0, _ = gpu_sweep(T, P, prec, thin=True, periodic=True)
+        compare(g0, j0, f0, i0, tol, name=f"{P.name} periodic thin prec {prec}")
+        g1, j1, _ = gpu_sweep(T, P, prec, f_prev=f0, periodic=True)
+        compare(g1, j1, f1, i1, tol, front=None if prec == T.TR_FP64 else front_mask(P, f1),
+                name=f"{P.name} periodic absorbing prec {prec}")
+
+
 def test_errors(T):
     P = W.small_uniform(16)
     ctx = T.context_for(P, T.TR_FP64)
