@@ -50,6 +50,8 @@ VALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
 #          2 per ray and 30 per target for the sum over rays and the self term
 NODE_BYTES = {"f32": 32, "f64": 60}
 TARGET_BYTES = 9
+# lanes per ray reported by the library -> the integration code of tr_set_launch
+INT_MODE = {1: 1, 64: 2, 4: 3, 8: 4, 16: 5}
 FLOP_TEST, FLOP_SUB, FLOP_NODE, FLOP_POINT, FLOP_RAY, FLOP_TARGET = 11, 56, 240, 20, 2, 30
 SRC_FILES = ["csrc/treeray.hip", "csrc/kernels.h", "csrc/tr_internal.h", "csrc/topology.cpp"]
 
@@ -164,7 +166,7 @@ def main():
                    accepted=int(acc), tested=int(tested), waves=st.waves_per_target,
                    per_cu=st.targets_per_cu, lds=st.buffer_in_lds, guard=int(st.guard_recomputes),
                    nr=st.n_radial_max, intw=st.integration_wave)
-        res["launch"] = f"{res['waves']},{res['per_cu']},{1 if res['lds'] else 2},{2 if res['intw'] else 1}"
+        res["launch"] = f"{res['waves']},{res['per_cu']},{1 if res['lds'] else 2},{INT_MODE[res['intw']]}"
         log(f"{name}: {res['ms_per_step']:.2f} ms/step, sweep {res['sweep_ms']:.2f} ms, launch {res['launch']}")
         # the same outer iteration as one hipGraph launch, ping-ponging two flux buffers
         a, b = f_prev.clone(), f_new

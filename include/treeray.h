@@ -106,7 +106,7 @@ typedef struct {
     int32_t waves_per_target, targets_per_cu;   /* launch shape of the last sweep */
     int32_t buffer_in_lds;      /* 1 if the last sweep kept its ray buffers in LDS */
     int32_t overflow;           /* nonzero if a walk list overflowed */
-    int32_t integration_wave;   /* 1 if the last sweep integrated a ray per wave, 0 a ray per lane */
+    int32_t integration_wave;   /* lanes that integrated one ray in the last sweep: 1, 4, 8, 16 or 64 */
     double last_sweep_ms;       /* device time of the last walk/map/integrate launch */
 } tr_stats;
 
@@ -177,8 +177,10 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec);
 /* Launch shape of the sweep: waves per target (1,2,4,8,16), resident
  * targets per compute unit (0 = as many as fit), where a target's ray
  * buffer lives (0 = LDS when it fits, 1 = LDS, 2 = device memory) and how
- * rays are integrated (0 = by the launch shape, 1 = a lane per ray, 2 = a
- * wave per ray with the ray's points on the lanes).  Zeros restore the
+ * rays are integrated (0 = tuned or default, 1 = a lane per ray, 2 = a wave
+ * per ray with the ray's points on the lanes, 3, 4, 5 = a group of 4, 8, 16
+ * lanes per ray with the ray's emitting points on the lanes, the default; a
+ * ray with more emitting points than that takes a wave).  Zeros restore the
  * tuned default.  Results do not depend on the shape beyond rounding. */
 tr_status tr_set_launch(tr_ctx *c, int32_t waves_per_target, int32_t targets_per_cu, int32_t buffer,
                         int32_t integration);

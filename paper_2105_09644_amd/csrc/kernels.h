@@ -68,6 +68,28 @@ __device__ inline double wave_sum(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Sum over aligned groups of G lanes (G = 4, 8 or 16, uniform) with every
+// lane of a group ending with the same bits: lane swaps inside quads
+// ([1,0,3,2], [2,3,0,1]), then the mirror inside 8 and inside 16 lanes; each
+// step adds two partial sums in either order, and addition commutes.  Call
+// with every lane active.
+template <int CTRL>
+__device__ inline double dpp_swap_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double group_sum(double v, int G)
+{
+    v += dpp_swap_d<0xB1>(v);
+    v += dpp_swap_d<0x4E>(v);
+    if (G >= 8) v += dpp_swap_d<0x141>(v);
+    if (G >= 16) v += dpp_swap_d<0x140>(v);
+    return v;
+}
+
 __device__ inline int wave_excl_scan(int v, int &total)
 {
     const int lane = lane_id();

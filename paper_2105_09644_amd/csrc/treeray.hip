@@ -351,6 +351,7 @@ struct SweepArgs {
     float guard_tol;
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
     int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
+    int32_t int_group;       // > 0: a group of this many lanes per ray (slots = emitting points)
     int32_t eps_kernel;      // emission kernel (K_F1 .. K_G; 0 or K_F3: two-point W_f,3)
     int32_t periodic;        // 1: every node through its periodic copy closest to the target
     int32_t mass_gauss;      // 1: W_g for A, E, V and the self term; 0: W_p
@@ -616,6 +617,102 @@ __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, 
     for (int h = 0; h < NH; ++h)
         if (live[h]) s += ph[h] * drcp(rp[h] * rp[h]);
     return wave_sum(s);
+}
+
+// The same march with a group of G lanes per ray (G = 4, 8 or 16), so that a
+// wave integrates 64/G rays at once: slot s of the group holds the ray's s-th
+// emitting point j (in pixel-row order) with its Phi_j in a register, and
+// F_{i+1} is a group sum.  Every lane of a group reads the same point's
+// moments.  kbase / tp: this lane's ray (has_ray false: none) and its
+// outermost emitting point; tmax: the largest tp of the wave (uniform).  A
+// ray with more than G emitting points is left alone (ovf set on its lanes,
+// the caller integrates it another way).  Returns F_{0,k} in internal flux
+// units on every lane of the group.  Call with every lane active.
+template <typename Real>
+__device__ double integrate_rays_group(const Real *b, int G, int kbase, int tp, bool has_ray, int tmax,
+                                       const double *r, const double *inv2r, int nr, int nrm, int nside, int zeta_g,
+                                       bool &ovf)
+{
+    const int lane = lane_id();
+    const int sl = lane & (G - 1);
+    const int g0 = lane - sl;   // first lane of the group
+    const uint32_t gmask = (uint32_t)((1ull << G) - 1ull);
+    const double inv4pi = 1.0 / (4.0 * kPi);
+    const double ns = (double)nside;
+    // emitting points 1 .. tp, G at a time; the group's n-th goes to slot n
+    int j = -1, cnt = 0;
+    for (int c0 = 1; c0 <= tmax; c0 += G) {
+        const int i = c0 + sl;
+        const bool em = has_ray && i <= tp && b[kbase + Q_EPS * nrm + i] > (Real)0;
+        const uint32_t gm = (uint32_t)(__ballot(em) >> g0) & gmask;
+        const int rank = sl - cnt;
+        if (rank >= 0 && rank < __popc(gm)) {
+            uint32_t x = gm;
+            for (int t = 0; t < rank; ++t) x &= x - 1u;
+            j = c0 + __ffs(x) - 1;
+        }
+        cnt += __popc(gm);
+    }
+    ovf = has_ray && cnt > G;
+    const bool act = has_ray && !ovf;
+    double rj = 0.0, i2rj = 0.0, epsj = 0.0;
+    if (act && j > 0) {
+        rj = r[j];
+        i2rj = inv2r[j];
+        epsj = (double)b[kbase + Q_EPS * nrm + j];
+    }
+    double ph = 0.0, a1 = 0.0, fb1 = 0.0;   // alpha and previous flux at r_{i+1}
+    bool live = false;
+    // the point's moments are fetched one step ahead (zero beyond tp)
+    Real nV = 0, nA = 0, nE = 0;
+    if (act && tmax <= tp) {
+        nV = b[kbase + Q_V * nrm + tmax];
+        nA = b[kbase + Q_A * nrm + tmax];
+        nE = b[kbase + Q_E * nrm + tmax];
+    }
+    for (int i = tmax; i >= 0; --i) {
+        const double Vi = (double)nV, Ai = (double)nA, Ei = (double)nE;
+        if (act && i >= 1 && i - 1 <= tp) {
+            nV = b[kbase + Q_V * nrm + i - 1];
+            nA = b[kbase + Q_A * nrm + i - 1];
+            nE = b[kbase + Q_E * nrm + i - 1];
+        }
+        double ai = 0.0, fbi = 0.0;
+        if (Vi > 0.0) {
+            const double rv = drcp(Vi);
+            ai = Ai * rv;
+            fbi = Ei * rv;
+        }
+        if (i <= nr - 2) {
+            const double ri = r[i], ri1 = r[i + 1];
+            double f = 0.0;
+            if (live && j >= i + 2) {
+                const double B = rj - ri1;
+                f = ph * drcp(B * B);
+            }
+            const double ftot = group_sum(f, G);   // F_{i+1} of the group's ray
+            double g = 0.0;
+            if (ftot > 0.0) {
+                g = 2.0 * drcp(ftot);
+                if (fb1 > 0.0) g = fmin(g, drcp(fb1));
+            }
+            const double aseg = 0.5 * (ai + a1) * (ri1 - ri) * (1.0 / 3.0);
+            if (live) {
+                const double A = rj - ri, B = rj - ri1;
+                double z = j >= i + 2 ? f * g : 1.0;
+                if (zeta_g) z *= fmin(1.0, ns * A * i2rj);
+                ph = fmax(0.0, ph - aseg * (A * A + A * B + B * B) * z);
+                live = ph > 0.0;
+            }
+        }
+        if (act && i >= 1 && j == i) {
+            ph = epsj * inv4pi;
+            live = true;
+        }
+        a1 = ai;
+        fb1 = fbi;
+    }
+    return group_sum(live ? ph * drcp(rj * rj) : 0.0, G);
 }
 
 // c_magic[n] = ceil(2^16 / n): (l * c_magic[n]) >> 16 == l / n for 0 <= l < 64, 1 <= n <= 64
@@ -1198,19 +1295,28 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         const int *per = a.periodic ? D.ext : nullptr;
         if (wave == 0) walk_target(a, D.root, per, tx, ty, tz, fr0, fr1, acc, sc, fmax, amax, n_test);
         for (;;) {
-            int start = 0;
-            if (lane == 0) start = atomicAdd(&sc[S_CLAIM], CHUNK);
+            // claims of CHUNK nodes; once the walk is done, smaller ones near the
+            // end of the list (a share of what is left), so the waves finish together
+            int start = 0, size = CHUNK;
+            if (lane == 0) {
+                if (lds_load(&sc[S_DONE])) {
+                    const int left = lds_load(&sc[S_TOTAL]) - lds_load(&sc[S_CLAIM]);
+                    size = min(CHUNK, max(4, left / (2 * WAVES)));
+                }
+                start = atomicAdd(&sc[S_CLAIM], size);
+            }
             start = __shfl(start, 0, 64);
+            size = __shfl(size, 0, 64);
             int end = 0;
             for (;;) {
                 const int avail = lds_load(&sc[S_AVAIL]);
-                if (avail >= start + CHUNK) {
-                    end = start + CHUNK;
+                if (avail >= start + size) {
+                    end = start + size;
                     break;
                 }
                 if (lds_load(&sc[S_DONE])) {
                     const int total = lds_load(&sc[S_TOTAL]);
-                    end = min(start + CHUNK, total);
+                    end = min(start + size, total);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
@@ -1243,7 +1349,52 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 
         // --- per-ray integration and the sum over rays (rays without emission give 0) ---
         double fsum = 0.0;
-        if (a.int_wave) {
+        if (a.int_group > 0) {
+            // a group of G lanes per ray: the s-th emitting ray in pixel order goes
+            // to wave (s / NG) % WAVES, group s % NG, so the rays of a target fill
+            // few waves
+            const int G = a.int_group, NG = 64 / G;
+            int n_emit = 0;
+            for (int base = 0; base < npix; base += 64)
+                n_emit += (int)__popcll(__ballot(base + lane < npix && top[base + lane] > 0));
+            for (int r0 = wave * NG; r0 < n_emit; r0 += NG * WAVES) {
+                int myk = -1, mytp = 0, tmax = 0, seen = 0;
+                for (int base = 0; base < npix && seen < r0 + NG; base += 64) {
+                    const int t = base + lane < npix ? top[base + lane] : 0;
+                    uint64_t m = __ballot(t > 0);
+                    while (m && seen < r0 + NG) {
+                        const int l = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        if (seen >= r0) {
+                            const int tk = __builtin_amdgcn_readlane(t, l);
+                            if (lane / G == seen - r0) {
+                                myk = base + l;
+                                mytp = tk;
+                            }
+                            tmax = max(tmax, tk);
+                        }
+                        ++seen;
+                    }
+                }
+                const bool has = myk >= 0;
+                bool ovf = false;
+                const double f = integrate_rays_group<Real>(buf, G, has ? myk * a.stride_k : 0, mytp, has, tmax, rd, rd2,
+                                                            nr, nrm, a.nside, a.zeta_g, ovf);
+                const bool head = (lane & (G - 1)) == 0;
+                if (head && has && !ovf) fsum += f;
+                // a ray with more emitting points than the group has lanes: a wave
+                uint64_t om = __ballot(head && ovf);
+                while (om) {
+                    const int l = __ffsll((unsigned long long)om) - 1;
+                    om &= om - 1;
+                    const int k = __builtin_amdgcn_readlane(myk, l), tk = __builtin_amdgcn_readlane(mytp, l);
+                    const double fw =
+                        nr > 64 ? integrate_ray_wave<Real, 2>(buf, k * a.stride_k, rd, rd2, nr, nrm, tk, a.nside, a.zeta_g)
+                                : integrate_ray_wave<Real, 1>(buf, k * a.stride_k, rd, rd2, nr, nrm, tk, a.nside, a.zeta_g);
+                    if (lane == 0) fsum += fw;
+                }
+            }
+        } else if (a.int_wave) {
             // a wave per ray, the emitting rays dealt round robin over the waves
             int seen = 0;
             for (int base = 0; base < npix; base += 64) {
@@ -1645,8 +1796,11 @@ struct LaunchPlan {
     int waves = 0, blocks = 0, per_cu = 0, fmax = 0, amax = 0, stride_k = 0;
     size_t lds = 0;
     bool ldsbuf = true;
-    bool intw = false;   // a wave per ray in the integration
+    int intm = 1;   // integration: 1 a lane per ray, 2 a wave per ray, 3/4/5 a group of 4/8/16 lanes
 };
+
+// lanes that integrate one ray in integration mode m
+inline int lanes_per_ray(int m) { return m == 2 ? 64 : (m >= 3 ? 4 << (m - 3) : 1); }
 
 tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int buf_req, int int_req, LaunchPlan &L)
 {
@@ -1690,10 +1844,12 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)L.fn, waves * 64, L.lds));
     if (occ <= 0) return fail(c, TR_EINVAL, "sweep kernel does not fit on a compute unit (LDS " + std::to_string(L.lds) + " B)");
     L.per_cu = tpc_req > 0 ? std::min(tpc_req, occ) : occ;
-    // integration: a wave per ray hides the march's latency when few targets
-    // share a compute unit; a lane per ray issues fewer instructions otherwise
-    int im = int_req > 0 ? int_req : c->tuned_int[f32 ? 1 : 0];
-    L.intw = im > 0 ? im == 2 : L.per_cu <= 2;
+    // integration: by default a group of lanes per ray, so that a target's few
+    // emitting rays share a wave (rays with more emitting points than the group
+    // has lanes take a wave): 16 lanes from N_side 4 on, where a ray crosses
+    // more nodes, else 8
+    const int im = int_req > 0 ? int_req : c->tuned_int[f32 ? 1 : 0];
+    L.intm = im > 0 ? im : (npix >= 192 ? 5 : 4);
     int64_t blocks = (int64_t)c->n_cu * L.per_cu;
     if (blocks > n_items) blocks = std::max<int64_t>(1, n_items);
     L.blocks = (int)blocks;
@@ -1763,7 +1919,8 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.nr_max = c->nr_max;
     a.stride_k = L.stride_k;
     a.zeta_g = c->p.zeta_g;
-    a.int_wave = L.intw ? 1 : 0;
+    a.int_wave = L.intm == 2 ? 1 : 0;
+    a.int_group = L.intm >= 3 ? lanes_per_ray(L.intm) : 0;
     a.eps_kernel = c->p.eps_kernel;
     a.periodic = c->p.periodic ? 1 : 0;
     a.mass_gauss = c->p.mass_kernel == 6 ? 1 : 0;
@@ -1793,7 +1950,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     c->last_waves = L.waves;
     c->last_tpc = L.per_cu;
     c->last_lds = L.ldsbuf ? 1 : 0;
-    c->last_intw = L.intw ? 1 : 0;
+    c->last_intw = lanes_per_ray(L.intm);
     return TR_OK;
 }
 
@@ -2324,8 +2481,10 @@ tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer, i
 {
     if (!c) return TR_EINVAL;
     if (buffer < 0 || buffer > 2) return fail(c, TR_EINVAL, "buffer must be 0 (auto), 1 (LDS) or 2 (device memory)");
-    if (integration < 0 || integration > 2)
-        return fail(c, TR_EINVAL, "integration must be 0 (auto), 1 (a lane per ray) or 2 (a wave per ray)");
+    if (integration < 0 || integration > 5)
+        return fail(c, TR_EINVAL,
+                    "integration must be 0 (auto), 1 (a lane per ray), 2 (a wave per ray) or 3, 4, 5 (a group of 4, 8, "
+                    "16 lanes per ray)");
     if (!(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16))
         return fail(c, TR_EINVAL, "waves per target must be 0, 1, 2, 4, 8 or 16");
     if (tpc < 0) return fail(c, TR_EINVAL, "targets per CU must be >= 0");
@@ -2341,6 +2500,7 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
 {
     if (!c) return TR_EINVAL;
     if (!c->built) return fail(c, TR_ESTATE, "tr_autotune needs tr_build first");
+    c->tuned_int[c->p.precision == TR_FP32C ? 1 : 0] = 0;   // the first stage times the default form
     // sample: every m-th cell in Morton order, enough to fill the chip a few times
     const int64_t want = std::min<int64_t>(c->n_cells, (int64_t)c->n_cu * 64);
     const int64_t step = std::max<int64_t>(1, c->n_cells / std::max<int64_t>(1, want));
@@ -2358,29 +2518,39 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
     const int cand[5] = {1, 2, 4, 8, 16};
     double best = INFINITY;
     int bw = 0, bb = 0, bi = 0;
+    // mean of two timed sweeps after one untimed; false if the shape does not run
+    auto timed = [&](int w, int bm, int im, double &ms_out) {
+        LaunchPlan L;
+        if (plan_sweep(c, (int64_t)tg.size(), w, 0, bm, im, L) != TR_OK) return false;
+        float ms = 0, tot = 0;
+        for (int rep = 0; rep < 3; ++rep) {
+            if (launch_sweep(c, dt, (int64_t)tg.size(), fo, nullptr, true, w, 0, bm, im) != TR_OK) return false;
+            if (hipEventSynchronize(c->ev1) != hipSuccess) return false;
+            (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+            if (rep > 0) tot += ms;
+        }
+        ms_out = tot / 2;
+        return true;
+    };
+    // waves and buffer place with the default integration, then the integration form
     for (int bm = 1; bm <= 2; ++bm)
-        for (int w : cand)
-            for (int im = 1; im <= 2; ++im) {
-                LaunchPlan L;
-                if (plan_sweep(c, (int64_t)tg.size(), w, 0, bm, im, L) != TR_OK) continue;
-                float ms = 0, tot = 0;
-                bool ok = true;
-                for (int rep = 0; rep < 3 && ok; ++rep) {
-                    if (launch_sweep(c, dt, (int64_t)tg.size(), fo, nullptr, true, w, 0, bm, im) != TR_OK) {
-                        ok = false;
-                        break;
-                    }
-                    if (hipEventSynchronize(c->ev1) != hipSuccess) { ok = false; break; }
-                    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
-                    if (rep > 0) tot += ms;
-                }
-                if (ok && tot / 2 < best) {
-                    best = tot / 2;
-                    bw = w;
-                    bb = bm;
-                    bi = im;
-                }
+        for (int w : cand) {
+            double ms;
+            if (timed(w, bm, 0, ms) && ms < best) {
+                best = ms;
+                bw = w;
+                bb = bm;
+                bi = 0;
             }
+        }
+    if (bw > 0)
+        for (int im : {1, 2, 3, 4, 5}) {
+            double ms;
+            if (timed(bw, bb, im, ms) && ms < best) {
+                best = ms;
+                bi = im;
+            }
+        }
     dfree(dt);
     dfree(fo);
     c->err.clear();
