@@ -14,12 +14,13 @@ sample of targets on the host and gives the reported error of both forms.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--config 1..5] [--forms both|fp32c|fp64]
-                    [--launch-fp32c W,T,B,I] [--launch-fp64 W,T,B,I] [--copy-mib M]
+                    [--launch-fp32c W,T,B,I,A] [--launch-fp64 W,T,B,I,A] [--copy-mib M]
                     [--theta T] [--theta-if T] [--theta-src T]
 
 --launch-* fix the sweep's launch shape (waves per target, targets per CU,
 buffer 1 = LDS / 2 = device memory, integration 1 = a lane per ray / 2 = a
-wave per ray) instead of autotuning it; --copy-mib
+wave per ray / 3, 4, 5 = a group of 4, 8, 16 lanes per ray, accumulation
+1 = hardware atomics / 2 = compare-and-swap) instead of autotuning it; --copy-mib
 adds plain device copies of known size, the calibration of the HBM byte
 counters in a profiled run.
 """
@@ -70,8 +71,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=98304, help="oracle targets in the CPU baseline")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--launch-fp32c", default="", help="W,T,B,I launch shape of the FP32C sweep")
-    ap.add_argument("--launch-fp64", default="", help="W,T,B,I launch shape of the FP64 sweep")
+    ap.add_argument("--launch-fp32c", default="", help="W,T,B,I,A launch shape of the FP32C sweep")
+    ap.add_argument("--launch-fp64", default="", help="W,T,B,I,A launch shape of the FP64 sweep")
     ap.add_argument("--copy-mib", type=int, default=0, help="plain copies of this size after the steps")
     ap.add_argument("--theta", type=float, default=None, help="override the opening angle")
     ap.add_argument("--theta-if", type=float, default=None, help="IF MAC opening angle")
@@ -165,8 +166,9 @@ def main():
         res = dict(ms_per_step=dt * 1e3, value=n_cells * npix / dt, sweep_ms=float(np.mean(sweep_ms)),
                    accepted=int(acc), tested=int(tested), waves=st.waves_per_target,
                    per_cu=st.targets_per_cu, lds=st.buffer_in_lds, guard=int(st.guard_recomputes),
-                   nr=st.n_radial_max, intw=st.integration_wave)
-        res["launch"] = f"{res['waves']},{res['per_cu']},{1 if res['lds'] else 2},{INT_MODE[res['intw']]}"
+                   nr=st.n_radial_max, intw=st.integration_wave, cas=st.lds_cas)
+        res["launch"] = (f"{res['waves']},{res['per_cu']},{1 if res['lds'] else 2},{INT_MODE[res['intw']]},"
+                         f"{2 if res['cas'] else 1}")
         log(f"{name}: {res['ms_per_step']:.2f} ms/step, sweep {res['sweep_ms']:.2f} ms, launch {res['launch']}")
         # the same outer iteration as one hipGraph launch, ping-ponging two flux buffers
         a, b = f_prev.clone(), f_new

@@ -107,6 +107,7 @@ typedef struct {
     int32_t buffer_in_lds;      /* 1 if the last sweep kept its ray buffers in LDS */
     int32_t overflow;           /* nonzero if a walk list overflowed */
     int32_t integration_wave;   /* lanes that integrated one ray in the last sweep: 1, 4, 8, 16 or 64 */
+    int32_t lds_cas;            /* 1 if the last sweep accumulated its LDS ray buffers by compare-and-swap */
     double last_sweep_ms;       /* device time of the last walk/map/integrate launch */
 } tr_stats;
 
@@ -180,10 +181,14 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec);
  * rays are integrated (0 = tuned or default, 1 = a lane per ray, 2 = a wave
  * per ray with the ray's points on the lanes, 3, 4, 5 = a group of 4, 8, 16
  * lanes per ray with the ray's emitting points on the lanes, the default; a
- * ray with more emitting points than that takes a wave).  Zeros restore the
- * tuned default.  Results do not depend on the shape beyond rounding. */
+ * ray with more emitting points than that takes a wave) and how the waves
+ * of a target accumulate into a shared FP32 buffer in LDS at 8 or 16 waves
+ * (0 = tuned or default, compare-and-swap at 16 waves; 1 = hardware atomic
+ * adds; 2 = compare-and-swap loops on the values' bits; elsewhere hardware
+ * atomics).  Zeros restore the tuned default.  Results do not depend on the
+ * shape beyond rounding. */
 tr_status tr_set_launch(tr_ctx *c, int32_t waves_per_target, int32_t targets_per_cu, int32_t buffer,
-                        int32_t integration);
+                        int32_t integration, int32_t atomics);
 
 /* Searches the launch shape for the current build and precision by timing
  * sweeps over a sample of targets; keeps the fastest.  best_ms_out may be NULL. */

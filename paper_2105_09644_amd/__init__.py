@@ -48,6 +48,7 @@ class Stats(C.Structure):
                 ("nodes_tested", C.c_int64), ("guard_recomputes", C.c_int64), ("n_radial_max", C.c_int32),
                 ("depth_max", C.c_int32), ("waves_per_target", C.c_int32), ("targets_per_cu", C.c_int32),
                 ("buffer_in_lds", C.c_int32), ("overflow", C.c_int32), ("integration_wave", C.c_int32),
+                ("lds_cas", C.c_int32),
                 ("last_sweep_ms", C.c_double)]
 
 
@@ -76,7 +77,7 @@ def load_library(path: str = LIB_PATH):
         "tr_step": ([vp, vp, vp, vp, vp, dp], C.c_int),
         "tr_solve": ([vp, vp, vp, vp, C.POINTER(C.c_int32), dp], C.c_int),
         "tr_set_precision": ([vp, C.c_int32], C.c_int),
-        "tr_set_launch": ([vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+        "tr_set_launch": ([vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_int),
         "tr_autotune": ([vp, dp], C.c_int),
         "tr_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
         "tr_sync": ([vp], C.c_int),
@@ -173,8 +174,9 @@ class Context:
     def set_precision(self, prec):
         self._check(self.L.tr_set_precision(self.h, int(prec)))
 
-    def set_launch(self, waves=0, targets_per_cu=0, buffer=0, integration=0):
-        self._check(self.L.tr_set_launch(self.h, int(waves), int(targets_per_cu), int(buffer), int(integration)))
+    def set_launch(self, waves=0, targets_per_cu=0, buffer=0, integration=0, atomics=0):
+        self._check(self.L.tr_set_launch(self.h, int(waves), int(targets_per_cu), int(buffer), int(integration),
+                                         int(atomics)))
 
     def autotune(self):
         ms = C.c_double()

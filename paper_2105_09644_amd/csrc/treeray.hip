@@ -367,13 +367,30 @@ struct SweepArgs {
 // ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
 enum { Q_EPS = 0, Q_A = 1, Q_E = 2, Q_V = 3 };
 
-template <typename Real, bool ATOMIC>
+// Accumulation into a ray buffer shared by the waves of a workgroup.  AM: 0 a
+// plain add (one wave), 1 a hardware atomic add, 2 (FP32 in LDS) an add by
+// compare-and-swap on the value's bits: the same correctly rounded FP32 sum
+// in some order, through integer LDS atomics, which this chip runs at a
+// higher rate than FP32 ones when many waves deposit at once.
+template <typename Real, int AM>
 __device__ inline void buf_add(Real *p, Real v)
 {
-    if constexpr (ATOMIC)
+    if constexpr (AM == 2 && sizeof(Real) == 4) {
+        unsigned *q = (unsigned *)p;
+        unsigned old = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (;;) {
+            unsigned seen = old;
+            const unsigned nv = __float_as_uint(__uint_as_float(old) + v);
+            if (__hip_atomic_compare_exchange_strong(q, &seen, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
+                break;
+            old = seen;
+        }
+    } else if constexpr (AM != 0) {
         __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    else
+    } else {
         *p += v;
+    }
 }
 
 // Periodic boundaries (Sec. 2.8): v is twice a node centre's offset from the
@@ -817,7 +834,7 @@ __device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, 
 // The evaluation points are r_i = c i^2; the per-node loop recomputes them
 // in registers, so it makes no memory round trip besides its atomics.
 // KV: the radial-kernel variants of App. A (otherwise two-point W_f,3 and W_p)
-template <typename Real, bool ATOMIC, bool KV>
+template <typename Real, int ATOMIC, bool KV>
 __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *per, const Real *rt, int nr, Real rc_inv,
                           Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
 {
@@ -1015,6 +1032,7 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
             }
             ++nd;
         }
+        const int slot_kc = slot_k | (slot_c << 16);   // pixel < 2^16, count <= 64: one shuffle per batch
         // emission: lane q deposits pixel q's share on the two bracket points
         // (the spread forms go with A, E, V below); the ray's outermost emitting point
         if (has_eps && lane < nd) {
@@ -1024,12 +1042,13 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
                 if (je0 != (Real)0) buf_add<Real, ATOMIC>(row, wk * je0);
                 if (je1 != (Real)0) buf_add<Real, ATOMIC>(row + 1, wk * je1);
             }
-            top_max<ATOMIC>(top + slot_k, jetop);
+            top_max<ATOMIC != 0>(top + slot_k, jetop);
         }
         // A, E, V: lanes cover (pixel slot, point) pairs, G slots at a time
         for (int b0 = 0; b0 < nd; b0 += G) {
             const int q = b0 + po;
-            const int kq = __shfl(slot_k, q & 63, 64), cq = __shfl(slot_c, q & 63, 64);
+            const int kc = __shfl(slot_kc, q & 63, 64);
+            const int kq = kc & 0xffff, cq = kc >> 16;
             if (lane_ok && q < nd) {
                 const Real wk = (Real)cq * inv_s3;
                 Real *row = buf + (size_t)kq * a.stride_k + col;
@@ -1152,11 +1171,11 @@ __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx
 
 // The sweep of one launch.  FALLBACK: the second pass over the items whose
 // walk lists did not fit in LDS, with the lists in device memory.
-template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK, bool KV>
+template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK, bool KV, bool CAS = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     using R4 = typename R4T<Real>::T;
-    constexpr bool ATOMIC = WAVES > 1;
+    constexpr int ATOMIC = WAVES == 1 ? 0 : (CAS ? 2 : 1);
     constexpr int CHUNK = WAVES > 4 ? 16 : 32;   // nodes claimed at a time by a mapping wave
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1469,6 +1488,19 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_kv_fallback(SweepArgs a
     sweep_body<Real, WAVES, LDSBUF, true, true>(a);
 }
 
+// FP32 ray buffers in LDS accumulated by compare-and-swap (8 and 16 waves)
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_cas(SweepArgs a)
+{
+    sweep_body<float, WAVES, true, false, false, true>(a);
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_cas_fallback(SweepArgs a)
+{
+    sweep_body<float, WAVES, true, true, false, true>(a);
+}
+
 // ---------------------------------------------------------------------------
 // a9. delta_cell per domain.  The median is the lower median of the domain's
 // previous flux, found exactly by an 8-pass radix select over the IEEE bit
@@ -1625,11 +1657,12 @@ struct tr_ctx {
     // state
     bool built = false;
     tr_precision built_prec = TR_FP64;
-    int32_t waves = 0, tpc = 0, bufmode = 0, intmode = 0;   // user launch shape (0 = default)
-    int32_t last_waves = 0, last_tpc = 0, last_lds = 0, last_intw = 0;
+    int32_t waves = 0, tpc = 0, bufmode = 0, intmode = 0, atommode = 0;   // user launch shape (0 = default)
+    int32_t last_waves = 0, last_tpc = 0, last_lds = 0, last_intw = 0, last_cas = 0;
     int tuned_waves[2] = {0, 0};         // per precision after tr_autotune
     int tuned_buf[2] = {0, 0};
     int tuned_int[2] = {0, 0};
+    int tuned_atom[2] = {0, 0};
     float last_ms = 0.f;
     bool timed_valid = false;            // ev0/ev1 bracket a recorded sweep
     // one outer iteration captured as a hipGraph (tr_step)
@@ -1771,6 +1804,12 @@ KernelFn pick_kernel_kv(int waves, bool ldsbuf, bool fallback)
     return nullptr;
 }
 
+KernelFn pick_kernel_cas(int waves, bool fallback)
+{
+    if (waves == 8) return fallback ? (KernelFn)k_sweep_cas_fallback<8> : (KernelFn)k_sweep_cas<8>;
+    return fallback ? (KernelFn)k_sweep_cas_fallback<16> : (KernelFn)k_sweep_cas<16>;
+}
+
 template <typename Real>
 KernelFn pick_kernel(int waves, bool ldsbuf, bool fallback)
 {
@@ -1796,13 +1835,15 @@ struct LaunchPlan {
     int waves = 0, blocks = 0, per_cu = 0, fmax = 0, amax = 0, stride_k = 0;
     size_t lds = 0;
     bool ldsbuf = true;
+    bool cas = false;   // FP32 LDS buffers accumulated by compare-and-swap
     int intm = 1;   // integration: 1 a lane per ray, 2 a wave per ray, 3/4/5 a group of 4/8/16 lanes
 };
 
 // lanes that integrate one ray in integration mode m
 inline int lanes_per_ray(int m) { return m == 2 ? 64 : (m >= 3 ? 4 << (m - 3) : 1); }
 
-tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int buf_req, int int_req, LaunchPlan &L)
+tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int buf_req, int int_req, LaunchPlan &L,
+                     int atom_req = 0)
 {
     const bool f32 = c->p.precision == TR_FP32C;
     const size_t real = f32 ? 4 : 8;
@@ -1838,6 +1879,15 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
         L.fn_fb = f32 ? pick_kernel<float>(waves, L.ldsbuf, true) : pick_kernel<double>(waves, L.ldsbuf, true);
     }
     if (!L.fn || !L.fn_fb) return fail(c, TR_EINVAL, "waves per target must be 1, 2, 4, 8 or 16");
+    // accumulation: compare-and-swap (FP32, LDS, 8 or 16 waves) by default at 16 waves
+    {
+        const int am = atom_req > 0 ? atom_req : (c->atommode > 0 ? c->atommode : c->tuned_atom[f32 ? 1 : 0]);
+        L.cas = f32 && L.ldsbuf && !kv && (waves == 8 || waves == 16) && (am > 0 ? am == 2 : waves == 16);
+        if (L.cas) {
+            L.fn = pick_kernel_cas(waves, false);
+            L.fn_fb = pick_kernel_cas(waves, true);
+        }
+    }
     HIPCHK(hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
     HIPCHK(hipFuncSetAttribute((const void *)L.fn_fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
     int occ = 0;
@@ -1875,14 +1925,14 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
 }
 
 tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_out, uint8_t *ion, bool timed,
-                       int waves_req, int tpc_req, int buf_req, int int_req)
+                       int waves_req, int tpc_req, int buf_req, int int_req, int atom_req = 0)
 {
     if (!c->built) return fail(c, TR_ESTATE, "tr_sweep needs tr_build first");
     if (c->built_prec != c->p.precision) return fail(c, TR_ESTATE, "precision changed since tr_build; build again");
     if (n == 0) return TR_OK;
     LaunchPlan L;
     tr_status s = plan_sweep(c, n, waves_req > 0 ? waves_req : c->waves, tpc_req > 0 ? tpc_req : c->tpc,
-                             buf_req > 0 ? buf_req : c->bufmode, int_req > 0 ? int_req : c->intmode, L);
+                             buf_req > 0 ? buf_req : c->bufmode, int_req > 0 ? int_req : c->intmode, L, atom_req);
     if (s) return s;
     SweepArgs a{};
     a.geo = c->geo;
@@ -1951,6 +2001,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     c->last_tpc = L.per_cu;
     c->last_lds = L.ldsbuf ? 1 : 0;
     c->last_intw = lanes_per_ray(L.intm);
+    c->last_cas = L.cas ? 1 : 0;
     return TR_OK;
 }
 
@@ -2477,9 +2528,11 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec)
     return TR_OK;
 }
 
-tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer, int32_t integration)
+tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer, int32_t integration, int32_t atomics)
 {
     if (!c) return TR_EINVAL;
+    if (atomics < 0 || atomics > 2)
+        return fail(c, TR_EINVAL, "atomics must be 0 (auto), 1 (hardware atomic adds) or 2 (compare-and-swap)");
     if (buffer < 0 || buffer > 2) return fail(c, TR_EINVAL, "buffer must be 0 (auto), 1 (LDS) or 2 (device memory)");
     if (integration < 0 || integration > 5)
         return fail(c, TR_EINVAL,
@@ -2492,6 +2545,7 @@ tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer, i
     c->tpc = tpc;
     c->bufmode = buffer;
     c->intmode = integration;
+    c->atommode = atomics;
     drop_graph(c);
     return TR_OK;
 }
@@ -2500,7 +2554,8 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
 {
     if (!c) return TR_EINVAL;
     if (!c->built) return fail(c, TR_ESTATE, "tr_autotune needs tr_build first");
-    c->tuned_int[c->p.precision == TR_FP32C ? 1 : 0] = 0;   // the first stage times the default form
+    c->tuned_int[c->p.precision == TR_FP32C ? 1 : 0] = 0;   // the first stages time the default forms
+    c->tuned_atom[c->p.precision == TR_FP32C ? 1 : 0] = 0;
     // sample: every m-th cell in Morton order, enough to fill the chip a few times
     const int64_t want = std::min<int64_t>(c->n_cells, (int64_t)c->n_cu * 64);
     const int64_t step = std::max<int64_t>(1, c->n_cells / std::max<int64_t>(1, want));
@@ -2519,12 +2574,12 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
     double best = INFINITY;
     int bw = 0, bb = 0, bi = 0;
     // mean of two timed sweeps after one untimed; false if the shape does not run
-    auto timed = [&](int w, int bm, int im, double &ms_out) {
+    auto timed = [&](int w, int bm, int im, double &ms_out, int am = 0) {
         LaunchPlan L;
-        if (plan_sweep(c, (int64_t)tg.size(), w, 0, bm, im, L) != TR_OK) return false;
+        if (plan_sweep(c, (int64_t)tg.size(), w, 0, bm, im, L, am) != TR_OK) return false;
         float ms = 0, tot = 0;
         for (int rep = 0; rep < 3; ++rep) {
-            if (launch_sweep(c, dt, (int64_t)tg.size(), fo, nullptr, true, w, 0, bm, im) != TR_OK) return false;
+            if (launch_sweep(c, dt, (int64_t)tg.size(), fo, nullptr, true, w, 0, bm, im, am) != TR_OK) return false;
             if (hipEventSynchronize(c->ev1) != hipSuccess) return false;
             (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
             if (rep > 0) tot += ms;
@@ -2551,6 +2606,16 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
                 bi = im;
             }
         }
+    // and the accumulation form where there is a choice (FP32 buffers in LDS, 8 or 16 waves)
+    int ba = 0;
+    if (bw >= 8 && bb == 1 && c->p.precision == TR_FP32C)
+        for (int am : {1, 2}) {
+            double ms;
+            if (timed(bw, bb, bi, ms, am) && ms < best) {
+                best = ms;
+                ba = am;
+            }
+        }
     dfree(dt);
     dfree(fo);
     c->err.clear();
@@ -2559,6 +2624,7 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
     c->tuned_waves[c->p.precision == TR_FP32C ? 1 : 0] = bw;
     c->tuned_buf[c->p.precision == TR_FP32C ? 1 : 0] = bb;
     c->tuned_int[c->p.precision == TR_FP32C ? 1 : 0] = bi;
+    c->tuned_atom[c->p.precision == TR_FP32C ? 1 : 0] = ba;
     drop_graph(c);
     if (best_ms) *best_ms = best;
     return TR_OK;
@@ -2584,6 +2650,7 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
     out->targets_per_cu = c->last_tpc;
     out->buffer_in_lds = c->last_lds;
     out->integration_wave = c->last_intw;
+    out->lds_cas = c->last_cas;
     out->overflow = q[1];
     float ms = 0;
     if (c->timed_valid && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) out->last_sweep_ms = ms;

@@ -367,23 +367,28 @@ def test_periodic_boundaries(T, orc, make):
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_launch_shapes(T, orc, prec):
     # every integration form (a lane, a wave, a group of 4, 8 or 16 lanes per
-    # ray), both buffer places and 1, 4 and 16 waves per target give the
-    # oracle's flux; 60 sources on 12 rays put more emitting points on a ray
-    # than a group of 4 or 8 lanes holds, so the wave fall-back runs too
+    # ray), both buffer places, 1, 4 and 16 waves per target and both
+    # accumulation forms give the oracle's flux; 60 sources on 12 rays put more
+    # emitting points on a ray than a group of 4 or 8 lanes holds, so the wave
+    # fall-back runs too
     P = W.small_lognormal(16, n_src=60, seed=7, nside=1, n_radial=24)
     f0, i0 = orc_sweep(orc, P, thin=True)
     f1, i1 = orc_sweep(orc, P, f_prev=f0)
     pr, tol = (T.TR_FP64, TOL64) if prec == "fp64" else (T.TR_FP32C, TOL32)
     front = None if prec == "fp64" else front_mask(P, f1)
-    for waves in (1, 4, 16):
-        for buf in (1, 2):
-            for im, lanes in ((1, 1), (2, 64), (3, 4), (4, 8), (5, 16)):
-                name = f"shape waves {waves} buffer {buf} integration {im}"
-                g0, j0, st = gpu_sweep(T, P, pr, thin=True, launch=(waves, 0, buf, im))
-                assert (st.waves_per_target, st.buffer_in_lds, st.integration_wave) == (waves, int(buf == 1), lanes)
-                compare(g0, j0, f0, i0, tol, name=name + " thin")
-                g1, j1, _ = gpu_sweep(T, P, pr, f_prev=f0, launch=(waves, 0, buf, im))
-                compare(g1, j1, f1, i1, tol, front=front, name=name + " absorbing")
+    shapes = [(w, b, im, 0) for w in (1, 4, 16) for b in (1, 2) for im in (1, 2, 3, 4, 5)]
+    shapes += [(w, 1, 0, am) for w in (8, 16) for am in (1, 2)]   # the accumulation forms
+    for waves, buf, im, am in shapes:
+        name = f"shape waves {waves} buffer {buf} integration {im} atomics {am}"
+        g0, j0, st = gpu_sweep(T, P, pr, thin=True, launch=(waves, 0, buf, im, am))
+        assert (st.waves_per_target, st.buffer_in_lds) == (waves, int(buf == 1))
+        if im:
+            assert st.integration_wave == {1: 1, 2: 64, 3: 4, 4: 8, 5: 16}[im]
+        cas = prec == "fp32c" and buf == 1 and waves in (8, 16) and (am == 2 or (am == 0 and waves == 16))
+        assert st.lds_cas == int(cas)
+        compare(g0, j0, f0, i0, tol, name=name + " thin")
+        g1, j1, _ = gpu_sweep(T, P, pr, f_prev=f0, launch=(waves, 0, buf, im, am))
+        compare(g1, j1, f1, i1, tol, front=front, name=name + " absorbing")
 
 
 def test_errors(T):
