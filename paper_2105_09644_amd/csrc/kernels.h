@@ -90,16 +90,19 @@ __device__ inline double group_sum(double v, int G)
     return v;
 }
 
-__device__ inline int wave_excl_scan(int v, int &total)
+// Exclusive prefix sum over the 64 lanes with DPP (no LDS): an inclusive
+// scan inside each row of 16 (row_shr 1, 2, 4, 8 with zeros shifted in), then
+// the row totals carried by the row broadcasts of lanes 15 and 31.
+__device__ inline int wave_excl_scan_dpp(int v, int &total)
 {
-    const int lane = lane_id();
     int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    total = __shfl(x, 63, 64);
+    x += dpp_shr1(x);
+    x += dpp_shr2(x);
+    x += dpp_shr4(x);
+    x += dpp_shr8(x);
+    x += dpp_bc15(x);
+    x += dpp_bc31(x);
+    total = __builtin_amdgcn_readlane(x, 63);
     return x - v;
 }
 

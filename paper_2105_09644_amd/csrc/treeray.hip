@@ -1145,7 +1145,7 @@ __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx
             const uint64_t macc = __ballot(acc_it);
             const int cacc = __popcll(macc);
             int tot = 0;
-            const int off = wave_excl_scan(nch, tot);
+            const int off = wave_excl_scan_dpp(nch, tot);
             if (nacc + cacc > amax || nn + tot > fmax) {
                 ovf = true;
                 break;
@@ -1239,7 +1239,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             sc[S_TOTAL] = 0;
         }
         __syncthreads();
-        const int64_t item = sc[S_ITEM];
+        const int64_t item = uniform(sc[S_ITEM]);   // the same on every lane: scalar loads below
         if (item >= n_items) break;
         const int64_t it = FALLBACK ? (int64_t)a.ovf[item] : item;
         const int64_t cell = a.targets ? a.targets[it] : (int64_t)a.order[it];
