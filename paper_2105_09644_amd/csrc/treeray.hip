@@ -393,6 +393,39 @@ __device__ inline void buf_add(Real *p, Real v)
     }
 }
 
+// Three adds at once (A, E, V of one ray point): in the compare-and-swap form
+// the three reads and then the three swaps are in flight together, and only a
+// swap that lost a race (another wave changed the value) is repeated.
+template <typename Real, int AM>
+__device__ inline void buf_add3(Real *p0, Real v0, Real *p1, Real v1, Real *p2, Real v2)
+{
+    if constexpr (AM == 2 && sizeof(Real) == 4) {
+        unsigned *q0 = (unsigned *)p0, *q1 = (unsigned *)p1, *q2 = (unsigned *)p2;
+        unsigned o0 = __hip_atomic_load(q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        unsigned o1 = __hip_atomic_load(q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        unsigned o2 = __hip_atomic_load(q2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        unsigned r0 = atomicCAS(q0, o0, __float_as_uint(__uint_as_float(o0) + v0));
+        unsigned r1 = atomicCAS(q1, o1, __float_as_uint(__uint_as_float(o1) + v1));
+        unsigned r2 = atomicCAS(q2, o2, __float_as_uint(__uint_as_float(o2) + v2));
+        while (r0 != o0) {
+            o0 = r0;
+            r0 = atomicCAS(q0, o0, __float_as_uint(__uint_as_float(o0) + v0));
+        }
+        while (r1 != o1) {
+            o1 = r1;
+            r1 = atomicCAS(q1, o1, __float_as_uint(__uint_as_float(o1) + v1));
+        }
+        while (r2 != o2) {
+            o2 = r2;
+            r2 = atomicCAS(q2, o2, __float_as_uint(__uint_as_float(o2) + v2));
+        }
+    } else {
+        buf_add<Real, AM>(p0, v0);
+        buf_add<Real, AM>(p1, v1);
+        buf_add<Real, AM>(p2, v2);
+    }
+}
+
 // Periodic boundaries (Sec. 2.8): v is twice a node centre's offset from the
 // target along an axis with period L finest cells; returns the multiple of L
 // (in finest cells) that moves the offset into (-L/2, L/2], the closest copy.
@@ -1052,9 +1085,7 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
             if (lane_ok && q < nd) {
                 const Real wk = (Real)cq * inv_s3;
                 Real *row = buf + (size_t)kq * a.stride_k + col;
-                buf_add<Real, ATOMIC>(row, wk * wa);
-                buf_add<Real, ATOMIC>(row + nrm, wk * we);
-                buf_add<Real, ATOMIC>(row + 2 * nrm, wk * wv);
+                buf_add3<Real, ATOMIC>(row, wk * wa, row + nrm, wk * we, row + 2 * nrm, wk * wv);
                 if (KV && wq != (Real)0) buf_add<Real, ATOMIC>(row - nrm, wk * wq);   // the emission row
             }
         }
