@@ -1124,7 +1124,9 @@ __device__ inline void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATO
 // coordinates, the product taken in FP64).  Accepted nodes are appended to
 // acc and published through sc[S_AVAIL] as each batch of tests completes, so
 // the other waves map them while the walk goes on.
-enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_COUNT = 16 };
+// S_PRE: the bank's item was claimed (and possibly walked, S_WALKED) ahead,
+// during the previous target's integration
+enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_PRE, S_WALKED, S_COUNT = 16 };
 
 __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx, int ty, int tz, int *fr0, int *fr1,
                             int *acc, int *sc, int fmax, int amax, double &n_test)
@@ -1248,8 +1250,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         acc = (int *)p;
         p += amax * sizeof(int);
     }
-    int *sc = (int *)p;
-    p += S_COUNT * sizeof(int);
+    int *sc = (int *)p;   // two banks of S_COUNT: the current target's and the next one's
+    p += 2 * S_COUNT * sizeof(int);
     double *red = (double *)p;
     p += WAVES * sizeof(double);
     int *top = (int *)p;   // per ray: outermost point holding emission (0: none)
@@ -1259,18 +1261,28 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         FALLBACK ? min((int64_t)__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
                    : a.n_items;
 
+    // a bank takes the next work item with its walk counters reset
+    auto claim = [&](int *b) {
+        b[S_ITEM] = atomicAdd(&a.queue[FALLBACK ? 2 : 0], 1);
+        b[S_AVAIL] = 0;
+        b[S_CLAIM] = 0;
+        b[S_DONE] = 0;
+        b[S_OVF] = 0;
+        b[S_TOTAL] = 0;
+        b[S_WALKED] = 0;
+    };
+    if (tid == 0) sc[S_PRE] = sc[S_COUNT + S_PRE] = 0;
+    int bank = 0;
+    int cached_dom = -1, cached_tsize = -1;   // whose radial tables the LDS holds
     for (;;) {
+        int *const scb = sc + bank * S_COUNT;
         __syncthreads();
         if (tid == 0) {
-            sc[S_ITEM] = atomicAdd(&a.queue[FALLBACK ? 2 : 0], 1);
-            sc[S_AVAIL] = 0;
-            sc[S_CLAIM] = 0;
-            sc[S_DONE] = 0;
-            sc[S_OVF] = 0;
-            sc[S_TOTAL] = 0;
+            if (!scb[S_PRE]) claim(scb);
+            scb[S_PRE] = 0;
         }
         __syncthreads();
-        const int64_t item = uniform(sc[S_ITEM]);   // the same on every lane: scalar loads below
+        const int64_t item = uniform(scb[S_ITEM]);   // the same on every lane: scalar loads below
         if (item >= n_items) break;
         const int64_t it = FALLBACK ? (int64_t)a.ovf[item] : item;
         const int64_t cell = a.targets ? a.targets[it] : (int64_t)a.order[it];
@@ -1296,24 +1308,31 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         const Real rc_inv = (Real)D.rc_inv;
         const Real rcoef = (Real)(1.0 / D.rc_inv);
 
-        // evaluation points and the self-term weights (W_p at d = 0, h = cell size)
-        for (int i = tid; i < nr; i += WAVES * 64) {
-            const double rv = a.r64[D.r_off + i];
-            rd[i] = rv;
-            rd2[i] = i > 0 ? 1.0 / (2.0 * rv) : 0.0;
-            if constexpr (sizeof(Real) == 4) rt[i] = a.r32[D.r_off + i];
-            else rt[i] = (Real)rv;
+        // evaluation points and the self-term weights (W_p at d = 0, h = cell size):
+        // kept in LDS while consecutive targets share the domain and cell size
+        if (dom != cached_dom) {
+            for (int i = tid; i < nr; i += WAVES * 64) {
+                const double rv = a.r64[D.r_off + i];
+                rd[i] = rv;
+                rd2[i] = i > 0 ? 1.0 / (2.0 * rv) : 0.0;
+                if constexpr (sizeof(Real) == 4) rt[i] = a.r32[D.r_off + i];
+                else rt[i] = (Real)rv;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (wave == 0) {
-            Real w0 = 0, w1 = 0;
-            if (lane < nr) w0 = smooth_kernel<Real>(KV && a.mass_gauss != 0, rt[lane] / (Real)tsize);
-            if (lane + 64 < nr) w1 = smooth_kernel<Real>(KV && a.mass_gauss != 0, rt[lane + 64] / (Real)tsize);
-            const Real sum = wave_sum(w0 + w1);
-            if (lane < nr) wself[lane] = w0 / sum;
-            if (lane + 64 < nr) wself[lane + 64] = w1 / sum;
+        if (dom != cached_dom || tsize != cached_tsize) {
+            if (wave == 0) {
+                Real w0 = 0, w1 = 0;
+                if (lane < nr) w0 = smooth_kernel<Real>(KV && a.mass_gauss != 0, rt[lane] / (Real)tsize);
+                if (lane + 64 < nr) w1 = smooth_kernel<Real>(KV && a.mass_gauss != 0, rt[lane + 64] / (Real)tsize);
+                const Real sum = wave_sum(w0 + w1);
+                if (lane < nr) wself[lane] = w0 / sum;
+                if (lane + 64 < nr) wself[lane + 64] = w1 / sum;
+            }
+            __syncthreads();
+            cached_dom = dom;
+            cached_tsize = tsize;
         }
-        __syncthreads();
         // ray buffer: zero emission, the target's own share of A, E, V
         {
             // every ray starts from the same 4 N_R values: lane l holds entries l + 64 m
@@ -1341,31 +1360,31 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         }
         __syncthreads();
 
-        // --- wave 0 walks; every wave (wave 0 once its walk is done) maps ---
+        // --- wave 0 walks (unless the target was walked ahead); every wave maps ---
         const int *per = a.periodic ? D.ext : nullptr;
-        if (wave == 0) walk_target(a, D.root, per, tx, ty, tz, fr0, fr1, acc, sc, fmax, amax, n_test);
+        if (wave == 0 && !scb[S_WALKED]) walk_target(a, D.root, per, tx, ty, tz, fr0, fr1, acc, scb, fmax, amax, n_test);
         for (;;) {
             // claims of CHUNK nodes; once the walk is done, smaller ones near the
             // end of the list (a share of what is left), so the waves finish together
             int start = 0, size = CHUNK;
             if (lane == 0) {
-                if (lds_load(&sc[S_DONE])) {
-                    const int left = lds_load(&sc[S_TOTAL]) - lds_load(&sc[S_CLAIM]);
+                if (lds_load(&scb[S_DONE])) {
+                    const int left = lds_load(&scb[S_TOTAL]) - lds_load(&scb[S_CLAIM]);
                     size = min(CHUNK, max(4, left / (2 * WAVES)));
                 }
-                start = atomicAdd(&sc[S_CLAIM], size);
+                start = atomicAdd(&scb[S_CLAIM], size);
             }
             start = __shfl(start, 0, 64);
             size = __shfl(size, 0, 64);
             int end = 0;
             for (;;) {
-                const int avail = lds_load(&sc[S_AVAIL]);
+                const int avail = lds_load(&scb[S_AVAIL]);
                 if (avail >= start + size) {
                     end = start + size;
                     break;
                 }
-                if (lds_load(&sc[S_DONE])) {
-                    const int total = lds_load(&sc[S_TOTAL]);
+                if (lds_load(&scb[S_DONE])) {
+                    const int total = lds_load(&scb[S_TOTAL]);
                     end = min(start + size, total);
                     break;
                 }
@@ -1377,7 +1396,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                                         n_guard);
         }
         __syncthreads();
-        if (sc[S_OVF]) {
+        if (scb[S_OVF]) {
             if (tid == 0) {
                 bool queued = false;
                 if (!FALLBACK && a.ovf) {
@@ -1395,19 +1414,23 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             }
             continue;
         }
-        n_acc += (wave == 0 && lane == 0) ? (double)sc[S_TOTAL] : 0.0;
+        n_acc += (wave == 0 && lane == 0) ? (double)scb[S_TOTAL] : 0.0;
 
-        // --- per-ray integration and the sum over rays (rays without emission give 0) ---
+        // --- per-ray integration and the sum over rays (rays without emission give 0),
+        // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
+        constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
         double fsum = 0.0;
-        if (a.int_group > 0) {
+        if (wave >= IW) {
+            // no rays here
+        } else if (a.int_group > 0) {
             // a group of G lanes per ray: the s-th emitting ray in pixel order goes
-            // to wave (s / NG) % WAVES, group s % NG, so the rays of a target fill
+            // to wave (s / NG) % IW, group s % NG, so the rays of a target fill
             // few waves
             const int G = a.int_group, NG = 64 / G;
             int n_emit = 0;
             for (int base = 0; base < npix; base += 64)
                 n_emit += (int)__popcll(__ballot(base + lane < npix && top[base + lane] > 0));
-            for (int r0 = wave * NG; r0 < n_emit; r0 += NG * WAVES) {
+            for (int r0 = wave * NG; r0 < n_emit; r0 += NG * IW) {
                 int myk = -1, mytp = 0, tmax = 0, seen = 0;
                 for (int base = 0; base < npix && seen < r0 + NG; base += 64) {
                     const int t = base + lane < npix ? top[base + lane] : 0;
@@ -1453,7 +1476,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 while (m) {
                     const int l = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1;
-                    if (seen % WAVES == wave) {
+                    if (seen % IW == wave) {
                         const int tk = __builtin_amdgcn_readlane(t, l);
                         const double f =
                             nr > 64 ? integrate_ray_wave<Real, 2>(buf, (base + l) * a.stride_k, rd, rd2, nr, nrm, tk,
@@ -1466,10 +1489,32 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 }
             }
         } else {
-            // a lane per ray: ray k on lane k % 64 of wave (k / 64) % WAVES
-            for (int k = wave * 64 + lane; k < npix; k += 64 * WAVES) {
+            // a lane per ray: ray k on lane k % 64 of wave (k / 64) % IW
+            for (int k = wave * 64 + lane; k < npix; k += 64 * IW) {
                 const int t = top[k];
                 if (t > 0) fsum += integrate_ray<Real>(buf, k * a.stride_k, rd, rd2, nr, nrm, t, a.nside, a.zeta_g);
+            }
+        }
+        // the next target: claimed and walked into the other bank by the last wave
+        // (the node lists and that bank are not in use until the next barrier)
+        if (wave == WAVES - 1) {
+            int *const nsc = sc + (bank ^ 1) * S_COUNT;
+            if (lane == 0) {
+                claim(nsc);
+                nsc[S_PRE] = 1;
+            }
+            const int64_t nitem = uniform(lds_load(&nsc[S_ITEM]));
+            if (nitem < n_items) {
+                const int64_t nit = FALLBACK ? (int64_t)a.ovf[nitem] : nitem;
+                const int64_t ncell = a.targets ? a.targets[nit] : (int64_t)a.order[nit];
+                if (ncell >= 0 && ncell < a.n_cells) {
+                    const int ndom = a.cell_dom[ncell];
+                    const int4 ng = a.geo[a.cell_node[ncell]];
+                    const int nsz = ng.w & kSizeMask;
+                    walk_target(a, a.doms[ndom].root, a.periodic ? a.doms[ndom].ext : nullptr, 2 * ng.x + nsz,
+                                2 * ng.y + nsz, 2 * ng.z + nsz, fr0, fr1, acc, nsc, fmax, amax, n_test);
+                    if (lane == 0) nsc[S_WALKED] = 1;
+                }
             }
         }
         fsum = wave_sum(fsum);
@@ -1483,6 +1528,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             a.f_out[o] = f * D.flux_unit;
             if (a.ion_out) a.ion_out[o] = f > 0.0 ? 1 : 0;
         }
+        bank ^= 1;
     }
     // statistics
     n_test = wave_sum(n_test);
@@ -1811,7 +1857,7 @@ size_t sweep_lds_bytes(size_t real, int npix, int stride_k, int nrm, int fmax, i
     b += 2 * (((size_t)nrm * real + 15) / 16) * 16;
     b += 2 * (size_t)nrm * 8;
     b += 2 * (size_t)fmax * 4 + (size_t)amax * 4;
-    b += 16 * 4;
+    b += 2 * 16 * 4;
     b += (size_t)waves * 8;
     b += (size_t)npix * 4;
     return b;
