@@ -104,7 +104,8 @@ typedef struct {
     int64_t guard_recomputes;   /* FP32C: angular sub-points re-evaluated in FP64 */
     int32_t n_radial_max, depth_max;
     int32_t waves_per_target, targets_per_cu;   /* launch shape of the last sweep */
-    int32_t buffer_in_lds;      /* 1 if the last sweep kept its ray buffers in LDS */
+    int32_t buffer_in_lds;      /* where the last sweep kept its ray buffers: 1 LDS, 0 device memory,
+                                   2 (FP32) the A, E, V rows in LDS and the emission rows in device memory */
     int32_t overflow;           /* nonzero if a walk list overflowed */
     int32_t integration_wave;   /* lanes that integrated one ray in the last sweep: 1, 4, 8, 16 or 64 */
     int32_t lds_cas;            /* 1 if the last sweep accumulated its LDS ray buffers by compare-and-swap */

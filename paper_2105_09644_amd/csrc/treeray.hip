@@ -347,6 +347,8 @@ struct SweepArgs {
     int32_t *queue;          // [0] next item, [1] overflow flag
     unsigned long long *stats;  // [0] accepted, [1] tested, [2] guard recomputes
     void *gbuf;              // ray buffers in global memory (when they do not fit in LDS)
+    void *ebuf;              // split LDS buffers: the emission rows, npix x nr_max per workgroup
+    int32_t split;           // 1: A, E, V rows in LDS (stride_k = 3 nr_max + 1), emission rows in ebuf
     double theta2, theta_if2, theta_src2;   // squared opening angles (0: criterion off)
     float guard_tol;
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
@@ -366,6 +368,21 @@ struct SweepArgs {
 
 // ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
 enum { Q_EPS = 0, Q_A = 1, Q_E = 2, Q_V = 3 };
+
+// Where ray k's rows live: A, E and V of point i at b[k stride + oa + (0, 1, 2) nrm + i],
+// the emission at e[k estride + i].  Either one buffer with four rows per ray
+// (e = b, estride = stride, oa = nrm), or, when four rows do not fit in LDS,
+// the A, E, V rows in LDS and the emission rows (written by emitting nodes
+// only) in a per-workgroup plane in device memory.
+template <typename Real>
+struct RayRows {
+    Real *b, *e;
+    int stride, estride, oa, nrm;
+    __device__ Real &A(int k, int i) const { return b[(size_t)k * stride + oa + i]; }
+    __device__ Real &E(int k, int i) const { return b[(size_t)k * stride + oa + nrm + i]; }
+    __device__ Real &V(int k, int i) const { return b[(size_t)k * stride + oa + 2 * nrm + i]; }
+    __device__ Real &eps(int k, int i) const { return e[(size_t)k * estride + i]; }
+};
 
 // Accumulation into a ray buffer shared by the waves of a workgroup.  AM: 0 a
 // plain add (one wave), 1 a hardware atomic add, 2 (FP32 in LDS) an add by
@@ -459,18 +476,18 @@ __device__ inline Real smooth_kernel(bool gauss, Real x)
 // Phi (photon rate per steradian) lives in the eps slot of a point once the
 // march has passed it; FP32 buffers keep it as a split double in the
 // (eps, A) slots, both consumed by then.
-__device__ inline double phi_load(double *b, int k, int j, int nrm) { return b[k + Q_EPS * nrm + j]; }
-__device__ inline void phi_store(double *b, int k, int j, int nrm, double v) { b[k + Q_EPS * nrm + j] = v; }
-__device__ inline double phi_load(float *b, int k, int j, int nrm)
+__device__ inline double phi_load(const RayRows<double> &R, int k, int j) { return R.eps(k, j); }
+__device__ inline void phi_store(const RayRows<double> &R, int k, int j, double v) { R.eps(k, j) = v; }
+__device__ inline double phi_load(const RayRows<float> &R, int k, int j)
 {
-    const uint32_t lo = __float_as_uint(b[k + Q_EPS * nrm + j]);
-    const uint32_t hi = __float_as_uint(b[k + Q_A * nrm + j]);
+    const uint32_t lo = __float_as_uint(R.eps(k, j));
+    const uint32_t hi = __float_as_uint(R.A(k, j));
     return __hiloint2double((int)hi, (int)lo);
 }
-__device__ inline void phi_store(float *b, int k, int j, int nrm, double v)
+__device__ inline void phi_store(const RayRows<float> &R, int k, int j, double v)
 {
-    b[k + Q_EPS * nrm + j] = __uint_as_float((uint32_t)__double2loint(v));
-    b[k + Q_A * nrm + j] = __uint_as_float((uint32_t)__double2hiint(v));
+    R.eps(k, j) = __uint_as_float((uint32_t)__double2loint(v));
+    R.A(k, j) = __uint_as_float((uint32_t)__double2hiint(v));
 }
 
 // 1/x in FP64: hardware estimate refined by two Newton steps (x > 0, finite)
@@ -493,7 +510,7 @@ __device__ inline double drcp(double x)
 // and the source at r_{i+1} itself takes zeta_s = zeta_d = 1.
 // Returns F_{0,k} in internal flux units.
 template <typename Real>
-__device__ double integrate_ray(Real *b, int kbase, const double *r, const double *inv2r, int nr, int nrm, int top,
+__device__ double integrate_ray(const RayRows<Real> &R, int k, const double *r, const double *inv2r, int nr, int top,
                                 int nside, int zeta_g)
 {
     const double inv4pi = 1.0 / (4.0 * kPi);
@@ -501,15 +518,14 @@ __device__ double integrate_ray(Real *b, int kbase, const double *r, const doubl
     uint64_t m0 = 0, m1 = 0;     // points j holding a live Phi_j
     double a1 = 0.0, fb1 = 0.0;  // alpha and previous flux at r_{i+1}
     // the point's buffer entries are fetched one step ahead
-    Real nV = b[kbase + Q_V * nrm + top], nA = b[kbase + Q_A * nrm + top], nE = b[kbase + Q_E * nrm + top],
-         nEps = b[kbase + Q_EPS * nrm + top];
+    Real nV = R.V(k, top), nA = R.A(k, top), nE = R.E(k, top), nEps = R.eps(k, top);
     for (int i = top; i >= 0; --i) {
         const double Vi = (double)nV, Ai = (double)nA, Ei = (double)nE, ei = (double)nEps;
         if (i > 0) {
-            nV = b[kbase + Q_V * nrm + i - 1];
-            nA = b[kbase + Q_A * nrm + i - 1];
-            nE = b[kbase + Q_E * nrm + i - 1];
-            nEps = b[kbase + Q_EPS * nrm + i - 1];
+            nV = R.V(k, i - 1);
+            nA = R.A(k, i - 1);
+            nE = R.E(k, i - 1);
+            nEps = R.eps(k, i - 1);
         }
         double ai = 0.0, fbi = 0.0;
         if (Vi > 0.0) {
@@ -528,7 +544,7 @@ __device__ double integrate_ray(Real *b, int kbase, const double *r, const doubl
                     m &= m - 1;
                     if (j >= i + 2) {
                         const double dd = r[j] - ri1;
-                        ftot += phi_load(b, kbase, j, nrm) * drcp(dd * dd);
+                        ftot += phi_load(R, k, j) * drcp(dd * dd);
                     }
                 }
             }
@@ -543,14 +559,14 @@ __device__ double integrate_ray(Real *b, int kbase, const double *r, const doubl
                 while (m) {
                     const int j = (h << 6) + __ffsll((unsigned long long)m) - 1;
                     m &= m - 1;
-                    double ph = phi_load(b, kbase, j, nrm);
+                    double ph = phi_load(R, k, j);
                     const double rj = r[j];
                     const double A = rj - ri, B = rj - ri1;
                     double z = 1.0;
                     if (j >= i + 2) z = ph * drcp(B * B) * g;
                     if (zeta_g) z *= fmin(1.0, ns * A * inv2r[j]);
                     ph = fmax(0.0, ph - aseg * (A * A + A * B + B * B) * z);
-                    phi_store(b, kbase, j, nrm, ph);
+                    phi_store(R, k, j, ph);
                     if (!(ph > 0.0)) {
                         if (j < 64) m0 &= ~(1ull << j);
                         else m1 &= ~(1ull << (j - 64));
@@ -559,7 +575,7 @@ __device__ double integrate_ray(Real *b, int kbase, const double *r, const doubl
             }
         }
         if (i >= 1 && ei > 0.0) {
-            phi_store(b, kbase, i, nrm, ei * inv4pi);
+            phi_store(R, k, i, ei * inv4pi);
             if (i < 64) m0 |= 1ull << i;
             else m1 |= 1ull << (i - 64);
         }
@@ -573,7 +589,7 @@ __device__ double integrate_ray(Real *b, int kbase, const double *r, const doubl
             const int j = (h << 6) + __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
             const double rj = r[j];
-            f0 += phi_load(b, kbase, j, nrm) * drcp(rj * rj);
+            f0 += phi_load(R, k, j) * drcp(rj * rj);
         }
     }
     return f0;
@@ -593,7 +609,7 @@ __device__ inline double point_value(const double v[2], int i)
 // total flux F_{i+1} is a wave reduction.  Phi stays in registers.  Returns
 // F_{0,k} (uniform) in internal flux units.
 template <typename Real, int NH>
-__device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, const double *inv2r, int nr, int nrm,
+__device__ double integrate_ray_wave(const RayRows<Real> &R, int k, const double *r, const double *inv2r, int nr,
                                      int top, int nside, int zeta_g)
 {
     const int lane = lane_id();
@@ -607,13 +623,13 @@ __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, 
         al[h] = fb[h] = ph[h] = ep[h] = rp[h] = i2r[h] = 0.0;
         live[h] = false;
         if (p < nr) {
-            const double V = (double)b[kbase + Q_V * nrm + p];
+            const double V = (double)R.V(k, p);
             if (V > 0.0) {
                 const double rv = drcp(V);
-                al[h] = (double)b[kbase + Q_A * nrm + p] * rv;
-                fb[h] = (double)b[kbase + Q_E * nrm + p] * rv;
+                al[h] = (double)R.A(k, p) * rv;
+                fb[h] = (double)R.E(k, p) * rv;
             }
-            ep[h] = (double)b[kbase + Q_EPS * nrm + p];
+            ep[h] = (double)R.eps(k, p);
             rp[h] = r[p];
             i2r[h] = inv2r[p];
         }
@@ -673,15 +689,14 @@ __device__ double integrate_ray_wave(const Real *b, int kbase, const double *r, 
 // wave integrates 64/G rays at once: slot s of the group holds the ray's s-th
 // emitting point j (in pixel-row order) with its Phi_j in a register, and
 // F_{i+1} is a group sum.  Every lane of a group reads the same point's
-// moments.  kbase / tp: this lane's ray (has_ray false: none) and its
+// moments.  k / tp: this lane's ray (has_ray false: none) and its
 // outermost emitting point; tmax: the largest tp of the wave (uniform).  A
 // ray with more than G emitting points is left alone (ovf set on its lanes,
 // the caller integrates it another way).  Returns F_{0,k} in internal flux
 // units on every lane of the group.  Call with every lane active.
 template <typename Real>
-__device__ double integrate_rays_group(const Real *b, int G, int kbase, int tp, bool has_ray, int tmax,
-                                       const double *r, const double *inv2r, int nr, int nrm, int nside, int zeta_g,
-                                       bool &ovf)
+__device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int tp, bool has_ray, int tmax,
+                                       const double *r, const double *inv2r, int nr, int nside, int zeta_g, bool &ovf)
 {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
@@ -693,7 +708,7 @@ __device__ double integrate_rays_group(const Real *b, int G, int kbase, int tp, 
     int j = -1, cnt = 0;
     for (int c0 = 1; c0 <= tmax; c0 += G) {
         const int i = c0 + sl;
-        const bool em = has_ray && i <= tp && b[kbase + Q_EPS * nrm + i] > (Real)0;
+        const bool em = has_ray && i <= tp && R.eps(k, i) > (Real)0;
         const uint32_t gm = (uint32_t)(__ballot(em) >> g0) & gmask;
         const int rank = sl - cnt;
         if (rank >= 0 && rank < __popc(gm)) {
@@ -709,23 +724,23 @@ __device__ double integrate_rays_group(const Real *b, int G, int kbase, int tp, 
     if (act && j > 0) {
         rj = r[j];
         i2rj = inv2r[j];
-        epsj = (double)b[kbase + Q_EPS * nrm + j];
+        epsj = (double)R.eps(k, j);
     }
     double ph = 0.0, a1 = 0.0, fb1 = 0.0;   // alpha and previous flux at r_{i+1}
     bool live = false;
     // the point's moments are fetched one step ahead (zero beyond tp)
     Real nV = 0, nA = 0, nE = 0;
     if (act && tmax <= tp) {
-        nV = b[kbase + Q_V * nrm + tmax];
-        nA = b[kbase + Q_A * nrm + tmax];
-        nE = b[kbase + Q_E * nrm + tmax];
+        nV = R.V(k, tmax);
+        nA = R.A(k, tmax);
+        nE = R.E(k, tmax);
     }
     for (int i = tmax; i >= 0; --i) {
         const double Vi = (double)nV, Ai = (double)nA, Ei = (double)nE;
         if (act && i >= 1 && i - 1 <= tp) {
-            nV = b[kbase + Q_V * nrm + i - 1];
-            nA = b[kbase + Q_A * nrm + i - 1];
-            nE = b[kbase + Q_E * nrm + i - 1];
+            nV = R.V(k, i - 1);
+            nA = R.A(k, i - 1);
+            nE = R.E(k, i - 1);
         }
         double ai = 0.0, fbi = 0.0;
         if (Vi > 0.0) {
@@ -868,10 +883,13 @@ __device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, 
 // in registers, so it makes no memory round trip besides its atomics.
 // KV: the radial-kernel variants of App. A (otherwise two-point W_f,3 and W_p)
 template <typename Real, int ATOMIC, bool KV>
-__device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *per, const Real *rt, int nr, Real rc_inv,
+__device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, const int *per, const Real *rt, int nr,
+                          Real rc_inv,
                           Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
 {
     using R4 = typename R4T<Real>::T;
+    // emission rows (few writes; in device memory when the A, E, V rows alone fill LDS): hardware atomics
+    constexpr int EATOMIC = ATOMIC != 0 ? 1 : 0;
     const int lane = lane_id();
     const Real xe = (Real)0.86602540378443864676;
     // ---------------- phase 1 ----------------
@@ -1050,7 +1068,6 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
                                                        jfb, rcoef, jd, jhinv, a.eps_kernel == K_G) *
                                   rdlane(qeps, j);
         }
-        const int col = Q_A * nrm + jlo + io;
         // --- distinct pixels: slot q (lane q of slot_k / slot_c) holds pixel k_q and its count ---
         uint64_t rem = act_mask;
         int nd = 0, slot_k = 0, slot_c = 0;
@@ -1071,9 +1088,9 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
         if (has_eps && lane < nd) {
             if (jemode == 0) {
                 const Real wk = (Real)slot_c * inv_s3;
-                Real *row = buf + (size_t)slot_k * a.stride_k + Q_EPS * nrm + jie;
-                if (je0 != (Real)0) buf_add<Real, ATOMIC>(row, wk * je0);
-                if (je1 != (Real)0) buf_add<Real, ATOMIC>(row + 1, wk * je1);
+                Real *row = &R.eps(slot_k, jie);
+                if (je0 != (Real)0) buf_add<Real, EATOMIC>(row, wk * je0);
+                if (je1 != (Real)0) buf_add<Real, EATOMIC>(row + 1, wk * je1);
             }
             top_max<ATOMIC != 0>(top + slot_k, jetop);
         }
@@ -1084,9 +1101,9 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
             const int kq = kc & 0xffff, cq = kc >> 16;
             if (lane_ok && q < nd) {
                 const Real wk = (Real)cq * inv_s3;
-                Real *row = buf + (size_t)kq * a.stride_k + col;
+                Real *row = &R.A(kq, jlo + io);
                 buf_add3<Real, ATOMIC>(row, wk * wa, row + nrm, wk * we, row + 2 * nrm, wk * wv);
-                if (KV && wq != (Real)0) buf_add<Real, ATOMIC>(row - nrm, wk * wq);   // the emission row
+                if (KV && wq != (Real)0) buf_add<Real, EATOMIC>(&R.eps(kq, jlo + io), wk * wq);   // the emission row
             }
         }
         if (jn > 64) {
@@ -1094,7 +1111,7 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
             for (int q = 0; q < nd; ++q) {
                 const int k = __builtin_amdgcn_readlane(slot_k, q);
                 const Real wk = (Real)__builtin_amdgcn_readlane(slot_c, q) * inv_s3;
-                Real *row = buf + (size_t)k * a.stride_k + Q_A * nrm + jlo;
+                Real *row = &R.A(k, jlo);
                 for (int i2 = 64 + lane; i2 < jn; i2 += 64) {
                     const int i = jlo + i2;
                     const Real w2 =
@@ -1106,7 +1123,7 @@ __device__ void map_nodes(const SweepArgs &a, Real *buf, int *top, const int *pe
                         const Real q2 = emission_weight<Real>(jemode, i, i2, jle, jne, rdlane(ea, j), rdlane(eb, j), jfb,
                                                               rcoef, jd, jhinv, a.eps_kernel == K_G) *
                                         rdlane(qeps, j);
-                        if (q2 != (Real)0) buf_add<Real, ATOMIC>(row - nrm + i2, wk * q2);
+                        if (q2 != (Real)0) buf_add<Real, EATOMIC>(&R.eps(k, jlo + i2), wk * q2);
                     }
                 }
             }
@@ -1223,6 +1240,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     } else {
         buf = (Real *)a.gbuf + (size_t)blockIdx.x * buf_elems;
     }
+    // split: three rows (A, E, V) per ray in buf, the emission rows in device memory
+    const bool split = LDSBUF && a.split != 0;
+    Real *const eplane = split ? (Real *)a.ebuf + (size_t)blockIdx.x * npix * nrm : buf;
+    const RayRows<Real> R{buf, eplane, a.stride_k, split ? nrm : a.stride_k, split ? 0 : nrm, nrm};
     Real *rt = (Real *)p;
     p += ((nrm * sizeof(Real) + 15) / 16) * 16;
     Real *wself = (Real *)p;
@@ -1335,14 +1356,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         }
         // ray buffer: zero emission, the target's own share of A, E, V
         {
-            // every ray starts from the same 4 N_R values: lane l holds entries l + 64 m
+            // every ray starts from the same 4 (split: 3) N_R values: lane l holds entries l + 64 m
             const Real inv_npix = (Real)1 / (Real)npix;
-            const int per_ray = 4 * nrm;
+            const int per_ray = (split ? 3 : 4) * nrm;
             Real val[4 * kMaxRadial / 64];
 #pragma unroll
             for (int m = 0; m < 4 * kMaxRadial / 64; ++m) {
                 const int e = lane + 64 * m;
-                const int row = e / nrm, i = e - row * nrm;
+                const int row = e / nrm + (split ? 1 : 0), i = e - (e / nrm) * nrm;
                 Real v = (Real)0;
                 if (e < per_ray && row != Q_EPS && i < nr) {
                     const Real mom = row == Q_A ? tB.x : row == Q_E ? tB.y : tB.z;
@@ -1357,6 +1378,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     if (64 * m < per_ray && lane + 64 * m < per_ray) dst[lane + 64 * m] = val[m];
             }
             for (int k = tid; k < npix; k += WAVES * 64) top[k] = 0;
+            if (split)
+                for (int e = tid; e < npix * nrm; e += WAVES * 64) eplane[e] = (Real)0;
         }
         __syncthreads();
 
@@ -1392,7 +1415,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             }
             end = uniform(end);
             if (end <= start) break;
-            map_nodes<Real, ATOMIC, KV>(a, buf, top, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
+            map_nodes<Real, ATOMIC, KV>(a, R, top, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
                                         n_guard);
         }
         __syncthreads();
@@ -1451,8 +1474,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 }
                 const bool has = myk >= 0;
                 bool ovf = false;
-                const double f = integrate_rays_group<Real>(buf, G, has ? myk * a.stride_k : 0, mytp, has, tmax, rd, rd2,
-                                                            nr, nrm, a.nside, a.zeta_g, ovf);
+                const double f = integrate_rays_group<Real>(R, G, has ? myk : 0, mytp, has, tmax, rd, rd2, nr, a.nside,
+                                                            a.zeta_g, ovf);
                 const bool head = (lane & (G - 1)) == 0;
                 if (head && has && !ovf) fsum += f;
                 // a ray with more emitting points than the group has lanes: a wave
@@ -1462,8 +1485,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     om &= om - 1;
                     const int k = __builtin_amdgcn_readlane(myk, l), tk = __builtin_amdgcn_readlane(mytp, l);
                     const double fw =
-                        nr > 64 ? integrate_ray_wave<Real, 2>(buf, k * a.stride_k, rd, rd2, nr, nrm, tk, a.nside, a.zeta_g)
-                                : integrate_ray_wave<Real, 1>(buf, k * a.stride_k, rd, rd2, nr, nrm, tk, a.nside, a.zeta_g);
+                        nr > 64 ? integrate_ray_wave<Real, 2>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g)
+                                : integrate_ray_wave<Real, 1>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g);
                     if (lane == 0) fsum += fw;
                 }
             }
@@ -1479,10 +1502,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     if (seen % IW == wave) {
                         const int tk = __builtin_amdgcn_readlane(t, l);
                         const double f =
-                            nr > 64 ? integrate_ray_wave<Real, 2>(buf, (base + l) * a.stride_k, rd, rd2, nr, nrm, tk,
-                                                                  a.nside, a.zeta_g)
-                                    : integrate_ray_wave<Real, 1>(buf, (base + l) * a.stride_k, rd, rd2, nr, nrm, tk,
-                                                                  a.nside, a.zeta_g);
+                            nr > 64 ? integrate_ray_wave<Real, 2>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g)
+                                    : integrate_ray_wave<Real, 1>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g);
                         if (lane == 0) fsum += f;
                     }
                     ++seen;
@@ -1492,7 +1513,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             // a lane per ray: ray k on lane k % 64 of wave (k / 64) % IW
             for (int k = wave * 64 + lane; k < npix; k += 64 * IW) {
                 const int t = top[k];
-                if (t > 0) fsum += integrate_ray<Real>(buf, k * a.stride_k, rd, rd2, nr, nrm, t, a.nside, a.zeta_g);
+                if (t > 0) fsum += integrate_ray<Real>(R, k, rd, rd2, nr, t, a.nside, a.zeta_g);
             }
         }
         // the next target: claimed and walked into the other bank by the last wave
@@ -1723,6 +1744,8 @@ struct tr_ctx {
     int32_t *err_flags = nullptr;
     void *gbuf = nullptr;
     size_t gbuf_bytes = 0;
+    void *ebuf = nullptr;   // emission rows of split LDS buffers
+    size_t ebuf_bytes = 0;
     int32_t *glist = nullptr;            // walk lists of the fallback pass
     int32_t *ovf = nullptr;              // items queued for it
     int64_t ovf_cap = 0;
@@ -1802,6 +1825,8 @@ void free_domains(tr_ctx *c)
     dfree(c->solve_tmp);
     dfree(c->gbuf);
     c->gbuf_bytes = 0;
+    dfree(c->ebuf);
+    c->ebuf_bytes = 0;
     dfree(c->glist);
     dfree(c->ovf);
     c->ovf_cap = 0;
@@ -1913,6 +1938,7 @@ struct LaunchPlan {
     size_t lds = 0;
     bool ldsbuf = true;
     bool cas = false;   // FP32 LDS buffers accumulated by compare-and-swap
+    bool split = false; // A, E, V rows in LDS, emission rows in device memory
     int intm = 1;   // integration: 1 a lane per ray, 2 a wave per ray, 3/4/5 a group of 4/8/16 lanes
 };
 
@@ -1926,7 +1952,6 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     const size_t real = f32 ? 4 : 8;
     const int npix = 12 * c->p.nside * c->p.nside;
     const int nrm = c->nr_max;
-    L.stride_k = 4 * nrm + 1;   // odd stride: ray k of lane k hits distinct banks
     int waves = waves_req;
     if (waves <= 0) {
         waves = c->tuned_waves[f32 ? 1 : 0];
@@ -1940,9 +1965,16 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     L.fmax = 512;
     L.amax = 2048;
     int bm = buf_req > 0 ? buf_req : c->tuned_buf[f32 ? 1 : 0];
-    const bool fits = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
-    if (bm == 1 && !fits) return fail(c, TR_EINVAL, "ray buffers do not fit in LDS for this N_PIX and N_R");
-    L.ldsbuf = bm == 2 ? false : fits;
+    // four rows per ray in LDS (odd stride: ray k of lane k hits distinct banks); else, in
+    // FP32, the A, E, V rows in LDS and the emission rows in device memory; else all in
+    // device memory
+    const int stride4 = 4 * nrm + 1, stride3 = 3 * nrm + 1;
+    const bool fits4 = sweep_lds_bytes(real, npix, stride4, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
+    const bool fits3 = f32 && !kv && sweep_lds_bytes(real, npix, stride3, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
+    if (bm == 1 && !fits4 && !fits3) return fail(c, TR_EINVAL, "ray buffers do not fit in LDS for this N_PIX and N_R");
+    L.ldsbuf = bm == 2 ? false : (fits4 || fits3);
+    L.split = L.ldsbuf && !fits4;
+    L.stride_k = L.split ? stride3 : stride4;
     if (!L.ldsbuf) {
         L.fmax = 1024;
         L.amax = 4096;
@@ -1989,13 +2021,25 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
         if (dalloc(c, (void **)&c->ovf, sizeof(int32_t) * (size_t)n_items)) return TR_ENOMEM;
         c->ovf_cap = n_items;
     }
+    // per-workgroup slabs for the larger of the two grids (the second pass has
+    // n_cu x min(per_cu, kFallbackPerCu) workgroups)
+    const size_t nblk = (size_t)std::max<int64_t>(L.blocks, (int64_t)c->n_cu * std::min(L.per_cu, kFallbackPerCu));
     if (!L.ldsbuf) {
-        const size_t need = (size_t)L.blocks * npix * L.stride_k * real;
+        const size_t need = nblk * npix * L.stride_k * real;
         if (need > c->gbuf_bytes) {
             dfree(c->gbuf);
             c->gbuf_bytes = 0;
             if (dalloc(c, &c->gbuf, need)) return TR_ENOMEM;
             c->gbuf_bytes = need;
+        }
+    }
+    if (L.split) {
+        const size_t need = nblk * npix * nrm * real;
+        if (need > c->ebuf_bytes) {
+            dfree(c->ebuf);
+            c->ebuf_bytes = 0;
+            if (dalloc(c, &c->ebuf, need)) return TR_ENOMEM;
+            c->ebuf_bytes = need;
         }
     }
     return TR_OK;
@@ -2032,6 +2076,8 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.queue = c->queue;
     a.stats = c->stats;
     a.gbuf = c->gbuf;
+    a.ebuf = c->ebuf;
+    a.split = L.split ? 1 : 0;
     a.theta2 = c->p.theta * c->p.theta;
     a.theta_if2 = c->p.theta_if > 0.0 ? c->p.theta_if * c->p.theta_if : 0.0;
     a.theta_src2 = c->p.theta_src > 0.0 ? c->p.theta_src * c->p.theta_src : 0.0;
@@ -2076,7 +2122,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     }
     c->last_waves = L.waves;
     c->last_tpc = L.per_cu;
-    c->last_lds = L.ldsbuf ? 1 : 0;
+    c->last_lds = L.ldsbuf ? (L.split ? 2 : 1) : 0;
     c->last_intw = lanes_per_ray(L.intm);
     c->last_cas = L.cas ? 1 : 0;
     return TR_OK;

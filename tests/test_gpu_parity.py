@@ -391,6 +391,27 @@ def test_launch_shapes(T, orc, prec):
         compare(g1, j1, f1, i1, tol, front=front, name=name + " absorbing")
 
 
+@pytest.mark.parametrize("waves", [4, 16])
+def test_split_ray_buffers(T, orc, waves):
+    # N_side 4 with 64 radial points: four rows per ray (197 KB) do not fit in
+    # LDS, three do, so the FP32C sweep keeps A, E, V in LDS and the emission
+    # rows in device memory; the FP64 sweep keeps everything in device memory
+    P = W.small_lognormal(16, n_src=6, seed=8, nside=4, n_radial=64)
+    f0, i0 = orc_sweep(orc, P, thin=True)
+    f1, i1 = orc_sweep(orc, P, f_prev=f0)
+    front = front_mask(P, f1)
+    for im in (0, 1, 2):
+        name = f"split waves {waves} integration {im}"
+        g0, j0, st = gpu_sweep(T, P, T.TR_FP32C, thin=True, launch=(waves, 0, 0, im, 0))
+        assert st.buffer_in_lds == 2
+        compare(g0, j0, f0, i0, TOL32, name=name + " thin")
+        g1, j1, _ = gpu_sweep(T, P, T.TR_FP32C, f_prev=f0, launch=(waves, 0, 0, im, 0))
+        compare(g1, j1, f1, i1, TOL32, front=front, name=name + " absorbing")
+    g1, j1, st = gpu_sweep(T, P, T.TR_FP64, f_prev=f0, launch=(waves, 0, 0, 0, 0))
+    assert st.buffer_in_lds == 0
+    compare(g1, j1, f1, i1, TOL64, name=f"fp64 waves {waves} device buffers")
+
+
 def test_errors(T):
     P = W.small_uniform(16)
     ctx = T.context_for(P, T.TR_FP64)
