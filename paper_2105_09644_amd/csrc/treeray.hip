@@ -490,14 +490,14 @@ __device__ inline void phi_store(const RayRows<float> &R, int k, int j, double v
     R.A(k, j) = __uint_as_float((uint32_t)__double2hiint(v));
 }
 
-// 1/x in FP64: hardware estimate refined by two Newton steps (x > 0, finite)
+// 1/x in FP64 for the ray march (x > 0, finite): the hardware estimate (relative
+// error below 2^-24 on this chip, measured) refined by one Newton step, which
+// squares the error: a few 1e-15, far inside the FP64 form's 1e-10 bound, with
+// two fewer dependent FMAs on the march's critical path
 __device__ inline double drcp(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
 }
 
 // One ray (Sec. 2.5), one lane: march inwards from the outermost point that
