@@ -316,6 +316,24 @@ def test_long_walks_use_device_lists(T, orc):
         assert st.nodes_accepted / P.total_cells() > 2048
 
 
+def test_few_targets_with_long_walks(T, orc):
+    # a short target list whose walks all overflow the LDS lists, with ray
+    # buffers in device memory (FP64, FP32C) or split (FP32C at N_side 4 with
+    # 64 points): the second pass runs more workgroups than the first, each
+    # with its own buffer slab
+    rng = np.random.default_rng(26)
+    cases = [(W.small_lognormal(16, n_src=2, seed=25), T.TR_FP64, 2, 0),
+             (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 2, 0),
+             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP32C, 1, 2)]
+    for P, prec, buf, where in cases:
+        tg = np.sort(rng.choice(P.total_cells(), 37, replace=False))
+        f0, i0 = orc_sweep(orc, P, thin=True, targets=tg, theta=0.05)
+        g0, j0, st = gpu_sweep(T, P, prec, thin=True, targets=tg, launch=(4, 0, buf, 0, 0), theta=0.05)
+        assert st.overflow == 0 and st.buffer_in_lds == where
+        assert st.nodes_accepted / len(tg) > 2048
+        compare(g0, j0, f0, i0, TOL64 if prec == T.TR_FP64 else TOL32, name=f"37 targets prec {prec} buffer {buf}")
+
+
 @pytest.mark.parametrize("radius_cells", [0.45, 1.7])
 def test_sphere_sources(T, orc, radius_cells):
     """Sources as uniform spheres (Sec. 2.7): the exact-volume deposit against
