@@ -1226,7 +1226,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     using R4 = typename R4T<Real>::T;
     constexpr int ATOMIC = WAVES == 1 ? 0 : (CAS ? 2 : 1);
-    constexpr int CHUNK = WAVES > 4 ? 16 : 32;   // nodes claimed at a time by a mapping wave
+    constexpr int CHUNK = 64;   // nodes claimed at a time by a mapping wave (one per lane in phase 1)
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar loops over waves' work
