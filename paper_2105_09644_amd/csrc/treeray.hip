@@ -780,13 +780,6 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
     return group_sum(live ? ph * drcp(rj * rj) : 0.0, G);
 }
 
-// c_magic[n] = ceil(2^16 / n): (l * c_magic[n]) >> 16 == l / n for 0 <= l < 64, 1 <= n <= 64
-__constant__ uint32_t c_magic[65] = {
-    0, 65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554, 5958, 5462, 5042, 4682, 4370, 4096,
-    3856, 3641, 3450, 3277, 3121, 2979, 2850, 2731, 2622, 2521, 2428, 2341, 2260, 2185, 2115, 2048, 1986,
-    1928, 1873, 1821, 1772, 1725, 1681, 1639, 1599, 1561, 1525, 1490, 1457, 1425, 1395, 1366, 1338, 1311,
-    1286, 1261, 1237, 1214, 1192, 1171, 1150, 1130, 1111, 1093, 1075, 1058, 1041, 1024};
-
 template <typename T>
 __device__ inline T rdlane(T v, int l)
 {
