@@ -457,4 +457,17 @@ def test_errors(T):
         ctx.sync()
     assert e.value.status == T.TR_EINVAL
     assert math.isnan(o[2].item()) and o[0].item() > 0
+    # launch options out of range; buffers that cannot fit in LDS at this size
+    for bad_launch in ((3, 0, 0, 0, 0), (4, -1, 0, 0, 0), (4, 0, 3, 0, 0), (4, 0, 0, 6, 0), (4, 0, 0, 0, 3)):
+        with pytest.raises(T.TreeRayError) as e:
+            ctx.set_launch(*bad_launch)
+        assert e.value.status == T.TR_EINVAL
+    ctx.close()
+    big = W.small_uniform(16, nside=8, n_radial=64)   # 768 rays of 64 points: 590 KB in FP64
+    ctx = T.context_for(big, T.TR_FP64)
+    ctx.set_launch(4, 0, 1, 0, 0)
+    ctx.build(torch.tensor(big.n_h[0], device="cuda"), thin=True)
+    with pytest.raises(T.TreeRayError) as e:
+        ctx.sweep(torch.zeros(ctx.n_cells, dtype=torch.float64, device="cuda"))
+    assert e.value.status == T.TR_EINVAL and "LDS" in str(e.value)
     ctx.close()
