@@ -184,7 +184,7 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec);
  * lanes per ray with the ray's emitting points on the lanes, the default; a
  * ray with more emitting points than that takes a wave) and how the waves
  * of a target accumulate into a shared FP32 buffer in LDS at 8 or 16 waves
- * (0 = tuned or default, compare-and-swap at 16 waves; 1 = hardware atomic
+ * (0 = tuned or default, compare-and-swap; 1 = hardware atomic
  * adds; 2 = compare-and-swap loops on the values' bits; elsewhere hardware
  * atomics).  Zeros restore the tuned default.  Results do not depend on the
  * shape beyond rounding. */

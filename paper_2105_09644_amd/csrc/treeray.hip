@@ -1948,7 +1948,7 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     int waves = waves_req;
     if (waves <= 0) {
         waves = c->tuned_waves[f32 ? 1 : 0];
-        if (waves <= 0) waves = npix >= 192 ? 8 : 4;
+        if (waves <= 0) waves = npix >= 192 ? 16 : 8;   // the tuned picks at N_side 4 and 2
     }
     // the radial-kernel variants are built for 4 and 8 waves per target only
     const bool kv = !((c->p.eps_kernel == 0 || c->p.eps_kernel == 3) && (c->p.mass_kernel == 0 || c->p.mass_kernel == 5));
@@ -1981,10 +1981,10 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
         L.fn_fb = f32 ? pick_kernel<float>(waves, L.ldsbuf, true) : pick_kernel<double>(waves, L.ldsbuf, true);
     }
     if (!L.fn || !L.fn_fb) return fail(c, TR_EINVAL, "waves per target must be 1, 2, 4, 8 or 16");
-    // accumulation: compare-and-swap (FP32, LDS, 8 or 16 waves) by default at 16 waves
+    // accumulation: compare-and-swap by default (FP32, LDS, 8 or 16 waves)
     {
         const int am = atom_req > 0 ? atom_req : (c->atommode > 0 ? c->atommode : c->tuned_atom[f32 ? 1 : 0]);
-        L.cas = f32 && L.ldsbuf && !kv && (waves == 8 || waves == 16) && (am > 0 ? am == 2 : waves == 16);
+        L.cas = f32 && L.ldsbuf && !kv && (waves == 8 || waves == 16) && (am > 0 ? am == 2 : true);
         if (L.cas) {
             L.fn = pick_kernel_cas(waves, false);
             L.fn_fb = pick_kernel_cas(waves, true);

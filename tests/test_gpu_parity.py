@@ -402,7 +402,7 @@ def test_launch_shapes(T, orc, prec):
         assert (st.waves_per_target, st.buffer_in_lds) == (waves, int(buf == 1))
         if im:
             assert st.integration_wave == {1: 1, 2: 64, 3: 4, 4: 8, 5: 16}[im]
-        cas = prec == "fp32c" and buf == 1 and waves in (8, 16) and (am == 2 or (am == 0 and waves == 16))
+        cas = prec == "fp32c" and buf == 1 and waves in (8, 16) and am != 1
         assert st.lds_cas == int(cas)
         compare(g0, j0, f0, i0, tol, name=name + " thin")
         g1, j1, _ = gpu_sweep(T, P, pr, f_prev=f0, launch=(waves, 0, buf, im, am))
