@@ -213,14 +213,15 @@ def main():
         tf = flops / sec / 1e12
         gbs = byts / sec / 1e9
         traffic = measured_traffic(P.name, "fp32c" if form == "f32" else "fp64", r["launch"])
+        kernel = "k_sweep_cas" if r["cas"] else "k_sweep"   # the instantiation that ran
         # the bound is the roofline that allows the lesser throughput
         t_alu = flops / (VALU_PEAK_TFLOPS[form] * 1e12)
         t_hbm = byts / (HBM_PEAK_GBS * 1e9)
         alu = {"bound": "alu", "achieved": round(tf, 3), "peak": VALU_PEAK_TFLOPS[form], "unit": "TFLOP/s",
-               "frac": round(tf / VALU_PEAK_TFLOPS[form], 4), "traffic": traffic, "kernel": "k_sweep",
+               "frac": round(tf / VALU_PEAK_TFLOPS[form], 4), "traffic": traffic, "kernel": kernel,
                "flops_per_launch": int(flops), "launch_ms": round(r["sweep_ms"], 3)}
         hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": "k_sweep",
+               "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kernel,
                "bytes_per_launch": int(byts), "launch_ms": round(r["sweep_ms"], 3)}
         return (alu, hbm) if t_alu >= t_hbm else (hbm, alu)
 
