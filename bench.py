@@ -103,6 +103,25 @@ def measured_traffic(workload, form, launch):
     return None
 
 
+def measured_valu_issue(workload, form, launch):
+    """The sweep's VALU issue utilisation (wave instructions per CU per clock) from the
+    committed issue-counter summary, if it was taken from the current kernel sources
+    and the same launch shape."""
+    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_sq_counters.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        text = fh.read()
+    if f"kernel sources digest: {source_digest()}" not in text:
+        return None
+    m = re.search(("--launch-fp32c" if form == "fp32c" else "--launch-fp64") + r" (\S+)", text)
+    if not m or m.group(1) != launch:
+        return None
+    sec = re.search(r"^" + form + r" \(.*?(?:\n\n|\Z)", text, re.S | re.M)
+    u = re.search(r"VALU issue utilisation: .*= ([0-9.]+)", sec.group(0)) if sec else None
+    return float(u.group(1)) if u else None
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -214,12 +233,14 @@ def main():
         gbs = byts / sec / 1e9
         traffic = measured_traffic(P.name, "fp32c" if form == "f32" else "fp64", r["launch"])
         kernel = "k_sweep_cas" if r["cas"] else "k_sweep"   # the instantiation that ran
+        issue = measured_valu_issue(P.name, "fp32c" if form == "f32" else "fp64", r["launch"])
         # the bound is the roofline that allows the lesser throughput
         t_alu = flops / (VALU_PEAK_TFLOPS[form] * 1e12)
         t_hbm = byts / (HBM_PEAK_GBS * 1e9)
         alu = {"bound": "alu", "achieved": round(tf, 3), "peak": VALU_PEAK_TFLOPS[form], "unit": "TFLOP/s",
                "frac": round(tf / VALU_PEAK_TFLOPS[form], 4), "traffic": traffic, "kernel": kernel,
-               "flops_per_launch": int(flops), "launch_ms": round(r["sweep_ms"], 3)}
+               "flops_per_launch": int(flops), "launch_ms": round(r["sweep_ms"], 3),
+               "valu_issue_utilisation": issue}
         hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kernel,
                "bytes_per_launch": int(byts), "launch_ms": round(r["sweep_ms"], 3)}
