@@ -202,6 +202,11 @@ tr_status tr_sync(tr_ctx *c);
 
 const char *tr_last_error(const tr_ctx *c);
 
+/* Digest of the sources the library was built from (16 hex digits; a static
+ * string, never NULL).  Bindings compare it with the sources they ship with
+ * and refuse a library built from other sources. */
+const char *tr_source_digest(void);
+
 void tr_destroy(tr_ctx *c);
 
 #ifdef __cplusplus

@@ -21,7 +21,7 @@ TR_FP64, TR_FP32C = 0, 1
 # every entry point of include/treeray.h
 SYMBOLS = ["tr_create", "tr_set_domains", "tr_cell_count", "tr_set_sources", "tr_build", "tr_sweep",
            "tr_sweep_targets", "tr_delta", "tr_step", "tr_solve", "tr_set_precision", "tr_set_launch", "tr_autotune",
-           "tr_get_stats", "tr_sync", "tr_last_error", "tr_destroy"]
+           "tr_get_stats", "tr_sync", "tr_last_error", "tr_destroy", "tr_source_digest"]
 
 
 class TreeRayError(RuntimeError):
@@ -56,13 +56,19 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Loads the HIP library; raises if it is missing (there is no CPU path)."""
+    """Loads the HIP library; raises if it is missing or was built from other
+    sources than those in the tree (there is no CPU path and no silent use of
+    a stale build)."""
     global _lib
     if _lib is not None:
         return _lib
+    from . import build as _build
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() or "
                           f"python -m paper_2105_09644_amd.build")
+    if _build.stale(path):
+        raise ImportError(f"{path} was built from other sources (digest {_build.library_digest(path)}, "
+                          f"sources {_build.source_digest()}); rebuild it with __graft_entry__.build()")
     L = C.CDLL(path)
     vp, dp, i64p, u8p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_uint8)
     sig = {
@@ -83,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "tr_sync": ([vp], C.c_int),
         "tr_last_error": ([vp], C.c_char_p),
         "tr_destroy": ([vp], None),
+        "tr_source_digest": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -1,6 +1,14 @@
-"""Builds ``libtreeray.so`` for gfx950 with hipcc (in-tree)."""
+"""Builds ``libtreeray.so`` for gfx950 with hipcc (in-tree).
+
+The library carries the digest of the sources it was built from
+(``tr_source_digest``); :func:`stale` compares it with the digest of the
+sources in the tree, so a library left over from older sources is refused
+by the binding instead of being used.
+"""
 from __future__ import annotations
 
+import ctypes
+import hashlib
 import os
 import subprocess
 import sys
@@ -25,10 +33,38 @@ FLAGS = [
 ]
 
 
+def source_files():
+    return ([os.path.join(CSRC, s) for s in SOURCES + HEADERS]
+            + [os.path.join(ROOT, "include", "treeray.h"), os.path.abspath(__file__)])
+
+
+def source_digest() -> str:
+    """First 16 hex digits of the SHA-256 over the library's sources and this build script."""
+    h = hashlib.sha256()
+    for f in source_files():
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def library_digest(path: str = LIB):
+    """The source digest compiled into the library at path (None if it has none)."""
+    try:
+        L = ctypes.CDLL(path)
+        f = L.tr_source_digest
+    except (OSError, AttributeError):
+        return None
+    f.restype = ctypes.c_char_p
+    f.argtypes = []
+    v = f()
+    return v.decode() if v else None
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs]
+    cmd = [HIPCC, *FLAGS, f'-DTR_SOURCE_DIGEST="{source_digest()}"', "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,12 +80,11 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def stale() -> bool:
-    if not os.path.exists(LIB):
+def stale(path: str = LIB) -> bool:
+    """True when the library at path is missing or was built from other sources."""
+    if not os.path.exists(path):
         return True
-    t = os.path.getmtime(LIB)
-    deps = [os.path.join(CSRC, s) for s in SOURCES + HEADERS] + [os.path.join(ROOT, "include", "treeray.h")]
-    return any(os.path.getmtime(d) > t for d in deps)
+    return library_digest(path) != source_digest()
 
 
 if __name__ == "__main__":

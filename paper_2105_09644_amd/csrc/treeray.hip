@@ -1028,7 +1028,11 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
             const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
             if (active) pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
         }
-        pix = pix < 0 ? 0 : (pix >= a.npix ? a.npix - 1 : pix);
+        if ((unsigned)pix >= (unsigned)a.npix) {
+            // cannot happen for a finite direction: reported, never written out of bounds
+            atomicOr(&a.queue[1], 4);
+            pix = 0;
+        }
         // --- radial weights: this lane serves support point lo + io of batch slot po ---
         const int jpk = rdlane(packed, j);
         const int jlo = jpk & 255, jn = (jpk >> 8) & 255, jie = jpk >> 16;
@@ -2008,7 +2012,10 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     if (!c->glist &&
         dalloc(c, (void **)&c->glist, sizeof(int32_t) * (size_t)c->n_cu * kFallbackPerCu * 3 * kGlobalList))
         return TR_ENOMEM;
+    // a captured step graph holds the scratch pointers as kernel arguments:
+    // it is dropped whenever one of them is reallocated below
     if (c->ovf_cap < n_items) {   // every item may need the second pass
+        drop_graph(c);
         dfree(c->ovf);
         c->ovf_cap = 0;
         if (dalloc(c, (void **)&c->ovf, sizeof(int32_t) * (size_t)n_items)) return TR_ENOMEM;
@@ -2020,6 +2027,7 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     if (!L.ldsbuf) {
         const size_t need = nblk * npix * L.stride_k * real;
         if (need > c->gbuf_bytes) {
+            drop_graph(c);
             dfree(c->gbuf);
             c->gbuf_bytes = 0;
             if (dalloc(c, &c->gbuf, need)) return TR_ENOMEM;
@@ -2029,6 +2037,7 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     if (L.split) {
         const size_t need = nblk * npix * nrm * real;
         if (need > c->ebuf_bytes) {
+            drop_graph(c);
             dfree(c->ebuf);
             c->ebuf_bytes = 0;
             if (dalloc(c, &c->ebuf, need)) return TR_ENOMEM;
@@ -2584,6 +2593,7 @@ tr_status tr_step(tr_ctx *c, const double *n_h, const double *f_prev, double *f_
     c->timed_valid = false;   // no timed sweep in a step
     int32_t flags[4];
     std::memcpy(flags, c->pinned, 16);
+    if (flags[3] & 4) return fail(c, TR_EHIP, "internal error: a HEALPix pixel index fell outside [0, N_PIX)");
     if (flags[3]) return fail(c, TR_EOVERFLOW, "a walk list overflowed; affected cells hold NaN");
     if (flags[0] & 1) return fail(c, TR_EINVAL, "a source lies outside its domain or has a bad rate");
     if (flags[0] & 2) return fail(c, TR_EINVAL, "n_h or f_prev holds a negative or non-finite value");
@@ -2736,12 +2746,12 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
     dfree(fo);
     c->err.clear();
     (void)hipGetLastError();
+    drop_graph(c);   // trial plans may have reallocated the scratch a graph refers to
     if (bw == 0) return fail(c, TR_EHIP, "no launch shape ran");
     c->tuned_waves[c->p.precision == TR_FP32C ? 1 : 0] = bw;
     c->tuned_buf[c->p.precision == TR_FP32C ? 1 : 0] = bb;
     c->tuned_int[c->p.precision == TR_FP32C ? 1 : 0] = bi;
     c->tuned_atom[c->p.precision == TR_FP32C ? 1 : 0] = ba;
-    drop_graph(c);
     if (best_ms) *best_ms = best;
     return TR_OK;
 }
@@ -2774,6 +2784,11 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
     return TR_OK;
 }
 
+#ifndef TR_SOURCE_DIGEST
+#define TR_SOURCE_DIGEST "unknown"
+#endif
+const char *tr_source_digest(void) { return TR_SOURCE_DIGEST; }
+
 tr_status tr_sync(tr_ctx *c)
 {
     if (!c) return TR_EINVAL;
@@ -2781,6 +2796,7 @@ tr_status tr_sync(tr_ctx *c)
     HIPCHK(hipGetLastError());
     int32_t q[2] = {0, 0};
     HIPCHK(hipMemcpy(q, c->queue, sizeof(q), hipMemcpyDeviceToHost));
+    if (q[1] & 4) return fail(c, TR_EHIP, "internal error: a HEALPix pixel index fell outside [0, N_PIX)");
     if (q[1] & 2) return fail(c, TR_EINVAL, "a target index lies outside [0, n_cells); those outputs hold NaN");
     if (q[1]) return fail(c, TR_EOVERFLOW, "a walk list overflowed; affected targets hold NaN");
     return TR_OK;

@@ -284,6 +284,38 @@ def test_graph_step_replays(T, orc):
         ctx.close()
 
 
+def test_graph_after_scratch_regrowth(T, orc):
+    """A captured step graph refers to the sweep's scratch memory (the overflow
+    queue, ray-buffer slabs).  A target list longer than the grid regrows that
+    scratch; the next step must capture again instead of replaying the old
+    graph.  theta = 0.05 sends every walk through the overflow queue."""
+    P = W.small_lognormal(16, n_src=2, seed=25)
+    f0, _ = orc_sweep(orc, P, thin=True, theta=0.05)
+    f1, i1 = orc_sweep(orc, P, f_prev=f0, theta=0.05)
+    ctx = T.context_for(P, T.TR_FP64, theta=0.05)
+    ctx.set_launch(4, 0, 2, 0, 0)
+    n = ctx.n_cells
+    nh = torch.tensor(P.n_h[0], device="cuda")
+    fp = torch.tensor(f0, device="cuda")
+    out = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ctx.step(nh, fp, out)
+    compare(out.cpu().numpy(), (out > 0).cpu().numpy().astype(np.uint8), f1, i1, TOL64, name="step before regrowth")
+    # 3 n targets (every cell three times): the overflow queue and slabs grow
+    tg = torch.arange(3 * n, dtype=torch.int64, device="cuda") % n
+    ft = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    ctx.build(nh, fp)
+    ctx.sweep_targets(tg, ft)
+    ctx.sync()
+    assert ctx.stats().overflow == 0
+    compare(ft.cpu().numpy()[:n], (ft[:n] > 0).cpu().numpy().astype(np.uint8), f1, i1, TOL64, name="long list")
+    out.fill_(-1.0)
+    ctx.step(nh, fp, out)
+    ctx.sync()
+    assert ctx.stats().overflow == 0
+    compare(out.cpu().numpy(), (out > 0).cpu().numpy().astype(np.uint8), f1, i1, TOL64, name="step after regrowth")
+    ctx.close()
+
+
 @pytest.mark.parametrize("theta_if,theta_src", [(0.25, 0.2), (1e-6, 1e-6)])
 def test_if_and_src_macs(T, orc, theta_if, theta_src):
     """IF MAC and Src MAC (Sec. 2.4) against the oracle, on a previous flux that

@@ -51,3 +51,23 @@ def test_binding_refuses_without_gpu():
     from paper_2105_09644_amd import workloads as W
     with pytest.raises(RuntimeError):
         T.context_for(W.small_uniform(8))
+
+
+def test_stale_library_is_refused(tmp_path, monkeypatch):
+    """A library whose compiled-in source digest differs from the sources in the
+    tree is refused by the binding (no silent use of an old build)."""
+    import shutil
+
+    import paper_2105_09644_amd as T
+    from paper_2105_09644_amd import build as B
+    if B.stale():
+        B.build()
+    assert not B.stale()
+    assert B.library_digest() == B.source_digest()
+    copy = str(tmp_path / "libtreeray.so")
+    shutil.copy(B.LIB, copy)
+    monkeypatch.setattr(T, "_lib", None)
+    monkeypatch.setattr(B, "source_digest", lambda: "0123456789abcdef")
+    assert B.stale(copy)
+    with pytest.raises(ImportError, match="other sources"):
+        T.load_library(copy)
