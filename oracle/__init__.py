@@ -65,6 +65,13 @@ def lib():
         L.orc_radial_points.argtypes = [C.POINTER(Domain), C.POINTER(Params), C.c_int32, dp]
         L.orc_sweep.argtypes = [C.POINTER(Domain), C.POINTER(Params), dp, C.c_int64, dp, dp, dp,
                                 C.c_int64, i64p, dp, u8p, C.POINTER(Stats)]
+        L.orc_sweep_timed.argtypes = [C.POINTER(Domain), C.POINTER(Params), dp, C.c_int64, dp, dp, dp,
+                                      C.c_int64, i64p, dp, u8p, C.POINTER(Stats), C.c_int32, dp]
+        L.orc_node_pixels.restype = C.c_int32
+        L.orc_node_pixels.argtypes = [C.c_int32, C.c_int32, i64p, i64p, dp, i64p, C.POINTER(C.c_int32)]
+        L.orc_target_rays.restype = C.c_int32
+        L.orc_target_rays.argtypes = [C.POINTER(Domain), C.POINTER(Params), dp, C.c_int64, dp, dp, dp, C.c_int64,
+                                      C.c_int32, dp, dp, dp, dp]
         L.orc_solve.argtypes = [C.POINTER(Domain), C.POINTER(Params), dp, C.c_int64, dp, dp,
                                 C.c_double, C.c_int32, dp, u8p, C.POINTER(C.c_int32), dp]
         L.orc_deposit.argtypes = [C.POINTER(Domain), C.c_int64, dp, dp, dp]
@@ -85,6 +92,8 @@ def lib():
         L.orc_ang2pix_many.argtypes = [C.c_int32, C.c_int64, dp, i64p]
         L.orc_num_threads.restype = C.c_int32
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [C.c_int32]
         L.orc_wp.restype = C.c_double
         L.orc_wp.argtypes = [C.c_double]
         L.orc_wp_weights.argtypes = [C.c_int32, dp, C.c_double, C.c_double, dp]
@@ -209,8 +218,10 @@ def ball_box_volume(centre, radius, lo, hi):
                                            _dp(lo), _dp(hi)))
 
 
-def sweep(dom, params, n_h, xyz, q, f_prev=None, targets=None, **over):
-    """One sweep; returns (F_tot per target, ionised flag per target, stats)."""
+def sweep(dom, params, n_h, xyz, q, f_prev=None, targets=None, threads=0, timing=None, **over):
+    """One sweep; returns (F_tot per target, ionised flag per target, stats).
+    threads > 0 runs the target loop on that many threads; a list passed as
+    timing receives the loop's wall time in seconds (tree build excluded)."""
     n = cell_count(dom)
     d, keep = _c_domain(dom)
     p = _c_params(params, **over)
@@ -226,10 +237,47 @@ def sweep(dom, params, n_h, xyz, q, f_prev=None, targets=None, **over):
     f = np.zeros(nt)
     ion = np.zeros(nt, np.uint8)
     st = Stats()
-    _check(lib().orc_sweep(C.byref(d), C.byref(p), _dp(n_h), len(q), _dp(xyz), _dp(q), _dp(fp),
-                           nt, tp, _dp(f), ion.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(st)),
+    sec = C.c_double(0.0)
+    _check(lib().orc_sweep_timed(C.byref(d), C.byref(p), _dp(n_h), len(q), _dp(xyz), _dp(q), _dp(fp),
+                                 nt, tp, _dp(f), ion.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(st),
+                                 int(threads), C.byref(sec)),
            "sweep")
+    if timing is not None:
+        timing.append(sec.value)
     return f, ion, st
+
+
+def node_pixels(nside, s, olo, ohi, xt):
+    """Angular weights of the node box [olo, ohi) (finest-cell units) seen from
+    the point xt: {pixel: sub-point count} over its s^3 sub-box midpoints."""
+    olo = np.ascontiguousarray(olo, dtype=np.int64)
+    ohi = np.ascontiguousarray(ohi, dtype=np.int64)
+    xt = np.ascontiguousarray(xt, dtype=np.float64)
+    pix = np.zeros(s ** 3, np.int64)
+    cnt = np.zeros(s ** 3, np.int32)
+    n = lib().orc_node_pixels(int(nside), int(s), olo.ctypes.data_as(C.POINTER(C.c_int64)),
+                              ohi.ctypes.data_as(C.POINTER(C.c_int64)), _dp(xt),
+                              pix.ctypes.data_as(C.POINTER(C.c_int64)), cnt.ctypes.data_as(C.POINTER(C.c_int32)))
+    _check(n, "node_pixels")
+    return {int(pix[k]): int(cnt[k]) for k in range(n)}
+
+
+def target_rays(dom, params, n_h, xyz, q, target, f_prev=None, **over):
+    """Mapped ray buffers of one target before the integration: (eps, A, E, V),
+    each [N_PIX, N_R], cgs, the self term included."""
+    d, keep = _c_domain(dom)
+    p = _c_params(params, **over)
+    n_h = np.ascontiguousarray(n_h, dtype=np.float64)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    fp = None if f_prev is None else np.ascontiguousarray(f_prev, dtype=np.float64)
+    npix = 12 * p.nside ** 2
+    cap = 1024
+    bufs = [np.zeros(npix * cap) for _ in range(4)]
+    nr = lib().orc_target_rays(C.byref(d), C.byref(p), _dp(n_h), len(q), _dp(xyz), _dp(q), _dp(fp), int(target),
+                               cap, *[_dp(b) for b in bufs])
+    _check(nr, "target_rays")
+    return tuple(b[:npix * nr].reshape(npix, nr).copy() for b in bufs)
 
 
 def solve(dom, params, n_h, xyz, q, eps_lim=1e-2, max_iter=30, **over):
@@ -322,3 +370,8 @@ def accepted(dom, params, n_h, xyz, q, target, f_prev=None, **over):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle sweeps (OpenMP)."""
+    lib().orc_set_num_threads(int(n))

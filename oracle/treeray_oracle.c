@@ -628,6 +628,16 @@ int32_t orc_num_threads(void)
 #endif
 }
 
+/* threads of later sweeps (n >= 1); the CPU baseline times one core and all */
+void orc_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads((int)n);
+#else
+    (void)n;
+#endif
+}
+
 void orc_ang2pix_many(int32_t nside, int64_t n, const double *xyz, int64_t *out)
 {
     for (int64_t q = 0; q < n; ++q) out[q] = orc_ang2pix(nside, xyz[3 * q], xyz[3 * q + 1], xyz[3 * q + 2]);
@@ -1009,6 +1019,50 @@ typedef struct {
     int *pc;                   /* their counts */
 } tbuf_t;
 
+/* Angular weights of one node (Sec. 2.3): the s^3 sub-box midpoints of the
+ * box with lower corner base and extent ext (finest units, base already
+ * moved to the copy in use) are classified by the HEALPix pixel of their
+ * direction from xt; returns the number of distinct pixels, listed in pl with
+ * their sub-point counts in pc. */
+static int node_pixels(int32_t nside, int s, const double base[3], const double ext[3], const double xt[3],
+                       int64_t *pl, int *pc)
+{
+    int npl = 0;
+    for (int ia = 0; ia < s; ++ia)
+        for (int ib = 0; ib < s; ++ib)
+            for (int ic = 0; ic < s; ++ic) {
+                int ii[3] = {ia, ib, ic};
+                double v[3];
+                for (int a = 0; a < 3; ++a) {
+                    double pa = base[a] + (((double)ii[a] + 0.5) + JIT[a]) * (ext[a] / (double)s);
+                    v[a] = pa - xt[a];
+                }
+                int64_t pix = orc_ang2pix(nside, v[0], v[1], v[2]);
+                int found = 0;
+                for (int k = 0; k < npl; ++k)
+                    if (pl[k] == pix) { pc[k]++; found = 1; break; }
+                if (!found) { pl[npl] = pix; pc[npl] = 1; ++npl; }
+            }
+    return npl;
+}
+
+int32_t orc_node_pixels(int32_t nside, int32_t s, const int64_t *olo, const int64_t *ohi, const double *xt,
+                        int64_t *pix_out, int32_t *count_out)
+{
+    if (nside < 1 || s < 1 || s > 64) return -1;
+    int *pc = (int *)malloc(sizeof(int) * (size_t)s * s * s);
+    if (!pc) return -2;
+    double base[3], ext[3];
+    for (int a = 0; a < 3; ++a) {
+        base[a] = (double)olo[a];
+        ext[a] = (double)(ohi[a] - olo[a]);
+    }
+    int n = node_pixels(nside, s, base, ext, xt, pix_out, pc);
+    for (int k = 0; k < n; ++k) count_out[k] = pc[k];
+    free(pc);
+    return n;
+}
+
 static void map_node(const walk_t *w, const onode_t *x, const cellq_t *q_override, int32_t nr,
                      const double *r, int64_t npix, tbuf_t *b)
 {
@@ -1020,23 +1074,12 @@ static void map_node(const walk_t *w, const onode_t *x, const cellq_t *q_overrid
     double sh[3];
     nearest_copy(w, x, sh);
     /* angular weights */
-    int npl = 0;
-    for (int ia = 0; ia < s; ++ia)
-        for (int ib = 0; ib < s; ++ib)
-            for (int ic = 0; ic < s; ++ic) {
-                int ii[3] = {ia, ib, ic};
-                double v[3];
-                for (int a = 0; a < 3; ++a) {
-                    double ext = (double)(x->ohi[a] - x->olo[a]);
-                    double pa = (double)(x->olo[a] + sh[a]) + (((double)ii[a] + 0.5) + JIT[a]) * (ext / (double)s);
-                    v[a] = pa - w->xt[a];
-                }
-                int64_t pix = orc_ang2pix(w->p->nside, v[0], v[1], v[2]);
-                int found = 0;
-                for (int k = 0; k < npl; ++k)
-                    if (b->pl[k] == pix) { b->pc[k]++; found = 1; break; }
-                if (!found) { b->pl[npl] = pix; b->pc[npl] = 1; ++npl; }
-            }
+    double base[3], ext[3];
+    for (int a = 0; a < 3; ++a) {
+        base[a] = (double)(x->olo[a] + sh[a]);
+        ext[a] = (double)(x->ohi[a] - x->olo[a]);
+    }
+    int npl = node_pixels(w->p->nside, s, base, ext, w->xt, b->pl, b->pc);
     /* radial weights */
     double d2 = 0;
     for (int a = 0; a < 3; ++a) {
@@ -1069,8 +1112,8 @@ typedef struct {
     const int64_t *node_of_cell;
 } sweep_ctx_t;
 
-static int sweep_target(const sweep_ctx_t *S, int64_t tc, tbuf_t *b, walk_t *w, double *fout,
-                        int64_t *n_acc, int64_t *n_tested)
+/* walk and map one target: its ray buffers, self term included */
+static int map_target(const sweep_ctx_t *S, int64_t tc, tbuf_t *b, walk_t *w, int64_t *n_acc, int64_t *n_tested)
 {
     const grid_t *g = S->g;
     int32_t nr = S->nr;
@@ -1101,6 +1144,21 @@ static int sweep_target(const sweep_ctx_t *S, int64_t tc, tbuf_t *b, walk_t *w, 
             b->E[k * nr + i] += ct->erad * wv;
             b->V[k * nr + i] += ct->vol * wv;
         }
+    *n_acc += w->nacc;
+    *n_tested += w->tested;
+    return 0;
+}
+
+static int sweep_target(const sweep_ctx_t *S, int64_t tc, tbuf_t *b, walk_t *w, double *fout,
+                        int64_t *n_acc, int64_t *n_tested)
+{
+    const grid_t *g = S->g;
+    int32_t nr = S->nr;
+    int64_t npix = 12 * (int64_t)S->p->nside * S->p->nside;
+    int rc = map_target(S, tc, b, w, n_acc, n_tested);
+    if (rc) return rc;
+    const cellq_t *ct = &S->cq[tc];
+    double dxt = (double)g->size[tc] * g->dx;
     double ftot = 0;
     for (int64_t k = 0; k < npix; ++k)
         ftot += orc_integrate_ray(nr, S->r, b->eps + k * nr, b->A + k * nr, b->E + k * nr,
@@ -1108,8 +1166,6 @@ static int sweep_target(const sweep_ctx_t *S, int64_t tc, tbuf_t *b, walk_t *w, 
     double rtp = 0.5 * dxt;
     ftot += 3.0 * ct->eps / (4.0 * ORC_PI * rtp * rtp);
     *fout = ftot;
-    *n_acc += w->nacc;
-    *n_tested += w->tested;
     return 0;
 }
 
@@ -1190,9 +1246,24 @@ int orc_sweep(const orc_domain *d, const orc_params *p, const double *n_h, int64
               int64_t n_targets, const int64_t *targets, double *f_out, uint8_t *ion_out,
               orc_stats *st)
 {
+    return orc_sweep_timed(d, p, n_h, n_src, src_xyz_cm, src_q, f_prev, n_targets, targets, f_out, ion_out,
+                           st, 0, NULL);
+}
+
+int orc_sweep_timed(const orc_domain *d, const orc_params *p, const double *n_h, int64_t n_src,
+                    const double *src_xyz_cm, const double *src_q, const double *f_prev,
+                    int64_t n_targets, const int64_t *targets, double *f_out, uint8_t *ion_out,
+                    orc_stats *st, int32_t threads, double *seconds)
+{
     prep_t P;
     int rc = prep(d, p, n_h, n_src, src_xyz_cm, src_q, f_prev, &P);
     if (rc) { prep_free(&P); return rc; }
+#ifdef _OPENMP
+    const int nthr = threads > 0 ? (int)threads : omp_get_max_threads();
+    const double t_start = omp_get_wtime();
+#else
+    (void)threads;
+#endif
     int64_t nt = targets ? n_targets : P.g.n;
     for (int64_t q = 0; targets && q < nt; ++q)
         if (targets[q] < 0 || targets[q] >= P.g.n) { prep_free(&P); return -1; }
@@ -1200,7 +1271,7 @@ int orc_sweep(const orc_domain *d, const orc_params *p, const double *n_h, int64
     int64_t npix = 12 * (int64_t)p->nside * p->nside;
     int64_t acc_sum = 0, tested_sum = 0;
     int err = 0;
-#pragma omp parallel reduction(+ : acc_sum, tested_sum)
+#pragma omp parallel reduction(+ : acc_sum, tested_sum) num_threads(nthr)
     {
         tbuf_t b;
         walk_t w;
@@ -1227,6 +1298,11 @@ int orc_sweep(const orc_domain *d, const orc_params *p, const double *n_h, int64
         tbuf_free(&b);
         free(w.acc);
     }
+#ifdef _OPENMP
+    if (seconds) *seconds = omp_get_wtime() - t_start;
+#else
+    if (seconds) *seconds = 0.0;
+#endif
     if (st) {
         st->nodes_accepted = acc_sum;
         st->nodes_tested = tested_sum;
@@ -1276,6 +1352,39 @@ int64_t orc_accepted(const orc_domain *d, const orc_params *p, const double *n_h
  * with a zero normaliser but a non-zero new value is not converged.
  * delta_tot is eq. delta:er:tot.                                           */
 /* ------------------------------------------------------------------------ */
+
+/* The mapped ray buffers of one target (walk, node mapping and self term,
+ * before the integration): eps, A, E, V as [N_PIX][N_R] each, in cgs. */
+int32_t orc_target_rays(const orc_domain *d, const orc_params *p, const double *n_h, int64_t n_src,
+                        const double *src_xyz_cm, const double *src_q, const double *f_prev, int64_t target,
+                        int32_t max_nr, double *eps_out, double *a_out, double *e_out, double *v_out)
+{
+    prep_t P;
+    int rc = prep(d, p, n_h, n_src, src_xyz_cm, src_q, f_prev, &P);
+    if (rc) { prep_free(&P); return rc; }
+    if (target < 0 || target >= P.g.n || P.nr > max_nr) { prep_free(&P); return -1; }
+    sweep_ctx_t S = {&P.g, &P.t, P.cq, p, P.r, P.nr, NULL};
+    int64_t npix = 12 * (int64_t)p->nside * p->nside;
+    tbuf_t b;
+    walk_t w;
+    memset(&b, 0, sizeof(b));
+    memset(&w, 0, sizeof(w));
+    rc = tbuf_alloc(&b, npix, P.nr, p->subsample);
+    int64_t na = 0, nt = 0;
+    if (!rc) rc = map_target(&S, target, &b, &w, &na, &nt);
+    if (!rc) {
+        size_t nbuf = (size_t)npix * P.nr;
+        memcpy(eps_out, b.eps, sizeof(double) * nbuf);
+        memcpy(a_out, b.A, sizeof(double) * nbuf);
+        memcpy(e_out, b.E, sizeof(double) * nbuf);
+        memcpy(v_out, b.V, sizeof(double) * nbuf);
+    }
+    tbuf_free(&b);
+    free(w.acc);
+    int32_t nr = P.nr;
+    prep_free(&P);
+    return rc ? rc : nr;
+}
 
 static int cmp_double(const void *a, const void *b)
 {

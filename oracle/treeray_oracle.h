@@ -67,6 +67,13 @@ int orc_sweep(const orc_domain *d, const orc_params *p, const double *n_h,
               const double *f_prev, int64_t n_targets, const int64_t *targets,
               double *f_out, uint8_t *ion_out, orc_stats *st);
 
+/* The same with the target loop on `threads` OpenMP threads (0: the default)
+ * and its wall time (tree build excluded) in *seconds if not NULL. */
+int orc_sweep_timed(const orc_domain *d, const orc_params *p, const double *n_h,
+                    int64_t n_src, const double *src_xyz_cm, const double *src_q,
+                    const double *f_prev, int64_t n_targets, const int64_t *targets,
+                    double *f_out, uint8_t *ion_out, orc_stats *st, int32_t threads, double *seconds);
+
 /* Outer iteration: a thin sweep, then sweeps fed with the last flux until
  * delta_cell < eps_lim or max_iter sweeps; returns the number of sweeps after
  * the thin one in *iters and the last delta in *delta. */
@@ -93,8 +100,9 @@ double orc_wg(double x);
 void orc_mass_weights(int32_t kind, int32_t n, const double *r, double d, double h, double *v_out);
 void orc_eps_weights(int32_t kind, int32_t n, const double *r, double d, double h, double *u_out);
 
-/* OpenMP threads a sweep uses */
+/* OpenMP threads a sweep uses, and setting them (n >= 1) */
 int32_t orc_num_threads(void);
+void orc_set_num_threads(int32_t n);
 
 /* ---- pieces exposed for the pin tests ---- */
 int64_t orc_ang2pix(int32_t nside, double x, double y, double z);
@@ -114,6 +122,17 @@ int64_t orc_accepted(const orc_domain *d, const orc_params *p, const double *n_h
                      int64_t n_src, const double *src_xyz_cm, const double *src_q,
                      const double *f_prev, int64_t target, int64_t max_out,
                      int64_t *lo_size_out /* [max][4] */, double *mom_out /* [max][9] */);
+
+/* angular weights of one node box [olo, ohi) (finest units) seen from xt:
+ * the distinct pixels of its s^3 sub-box midpoints and their counts (arrays of
+ * s^3 entries); returns the number of distinct pixels or <0 */
+int32_t orc_node_pixels(int32_t nside, int32_t s, const int64_t *olo, const int64_t *ohi, const double *xt,
+                        int64_t *pix_out, int32_t *count_out);
+/* mapped ray buffers of one target before the integration, [N_PIX][N_R]
+ * each (self term included); returns N_R or <0 */
+int32_t orc_target_rays(const orc_domain *d, const orc_params *p, const double *n_h, int64_t n_src,
+                        const double *src_xyz_cm, const double *src_q, const double *f_prev, int64_t target,
+                        int32_t max_nr, double *eps_out, double *a_out, double *e_out, double *v_out);
 
 #ifdef __cplusplus
 }
