@@ -163,6 +163,20 @@ def config3(n: int = 128) -> Problem:
     return Problem(f"lognormal{n}_16src_nside2", [dom], [nh], [xyz], [q], p)
 
 
+def source_count_problem(n_src: int, n: int = 128, q_total: float = 1.6e50) -> Problem:
+    """The config-3 grid (128^3 log-normal, sigma 1) with ``n_src`` sources at
+    seeded uniform-random positions sharing the total rate ``q_total`` equally:
+    the input of the source-count scaling (Sec. 5.2 measures 10 to 10^4 sources)."""
+    rng = rng_for(3)
+    dom = uniform_domain(n)
+    nh = lognormal_field(n, 1.0, 100.0, rng).ravel()
+    srng = rng_for(52, n_src)
+    xyz = srng.uniform(0.0, BOX_PC * PC_CM, size=(n_src, 3))
+    q = np.full(n_src, q_total / n_src)
+    p = Params(nside=2, n_radial=0, eta_r=2.0, theta=0.5)
+    return Problem(f"lognormal{n}_{n_src}src_equal_nside2", [dom], [nh], [xyz], [q], p)
+
+
 def config4(n_domains: int = 64, sizes=(32, 48, 64, 96)) -> Problem:
     """64 independent log-normal domains of uneven sizes, 1-8 sources each, N_PIX 48."""
     doms, nhs, xyzs, qs = [], [], [], []
@@ -307,6 +321,106 @@ X_H = 0.70                    # hydrogen mass fraction of the paper's gas (Sec. 
 def hydrogen_density(rho_g_cm3: float) -> float:
     """n_H of gas with mass density rho and hydrogen mass fraction X_H."""
     return X_H * rho_g_cm3 / M_P
+
+
+def cell_lo_size(dom: Domain):
+    """Lower corner (finest-cell units, int64 [n, 3]) and size (finest cells,
+    int64 [n]) of every leaf cell in the library's cell order."""
+    if dom.leaf_blocks is None:
+        e = dom.extent_finest()
+        ix, iy, iz = np.meshgrid(*[np.arange(e[a], dtype=np.int64) for a in range(3)], indexing="ij")
+        lo = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+        return lo, np.ones(lo.shape[0], np.int64)
+    lb = np.asarray(dom.leaf_blocks, dtype=np.int64)
+    csz = (1 << (dom.max_level - lb[:, 0]))                       # cell size of each block, finest cells
+    a = np.arange(BLOCK, dtype=np.int64)
+    ci, cj, ck = np.meshgrid(a, a, a, indexing="ij")
+    off = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)   # C order inside a block
+    lo = (lb[:, None, 1:4] * BLOCK + off[None, :, :]) * csz[:, None, None]
+    return lo.reshape(-1, 3), np.repeat(csz, BLOCK ** 3)
+
+
+def locate_cells(dom: Domain, pts: np.ndarray) -> np.ndarray:
+    """Leaf cell (library order) containing each point given in finest-cell
+    units ([m, 3], points strictly inside cells); -1 outside the domain."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    e = np.asarray(dom.extent_finest(), dtype=np.float64)
+    inside = np.all((pts >= 0) & (pts < e), axis=1)
+    out = np.full(pts.shape[0], -1, np.int64)
+    if dom.leaf_blocks is None:
+        q = np.floor(pts[inside]).astype(np.int64)
+        n = np.asarray(dom.extent_finest(), dtype=np.int64)
+        out[inside] = (q[:, 0] * n[1] + q[:, 1]) * n[2] + q[:, 2]
+        return out
+    lb = np.asarray(dom.leaf_blocks, dtype=np.int64)
+    L = dom.max_level
+    idx = np.nonzero(inside)[0]
+    for lev in range(L + 1):
+        if idx.size == 0:
+            break
+        sel = lb[:, 0] == lev
+        if not sel.any():
+            continue
+        bsz = BLOCK << (L - lev)                                   # block side, finest cells
+        nb = np.asarray(dom.nroot, dtype=np.int64) << lev          # blocks per axis at this level
+        bno = np.nonzero(sel)[0]
+        keys = (lb[bno, 1] * nb[1] + lb[bno, 2]) * nb[2] + lb[bno, 3]
+        order = np.argsort(keys)
+        keys, bno = keys[order], bno[order]
+        b = np.floor(pts[idx] / bsz).astype(np.int64)
+        k = (b[:, 0] * nb[1] + b[:, 1]) * nb[2] + b[:, 2]
+        j = np.clip(np.searchsorted(keys, k), 0, keys.size - 1)
+        hit = keys[j] == k
+        if hit.any():
+            blk = bno[j[hit]]
+            csz = 1 << (L - lev)
+            c = np.floor((pts[idx[hit]] - b[hit] * bsz) / csz).astype(np.int64)
+            out[idx[hit]] = blk * BLOCK ** 3 + (c[:, 0] * BLOCK + c[:, 1]) * BLOCK + c[:, 2]
+        idx = idx[~hit]
+    return out
+
+
+def cell_neighbours(dom: Domain, cells: np.ndarray) -> np.ndarray:
+    """The 26 neighbours of each listed cell ([m, 26], library order, -1
+    outside the domain): the leaf cells holding the points half a finest cell
+    beyond each face, edge and corner of the cell.  On an adaptive grid a
+    neighbour finer than the cell is the one touching that face/edge/corner's
+    centre."""
+    lo, size = cell_lo_size(dom)
+    cells = np.asarray(cells, dtype=np.int64)
+    c = lo[cells] + 0.5 * size[cells, None]
+    h = 0.5 * size[cells, None] + 0.5
+    dirs = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)
+                     if (i, j, k) != (0, 0, 0)], dtype=np.float64)
+    pts = c[:, None, :] + h[:, None, :] * dirs[None, :, :]
+    return locate_cells(dom, pts.reshape(-1, 3)).reshape(cells.size, 26)
+
+
+def sample_with_neighbours(dom: Domain, n_centres: int, rng: np.random.Generator, lit=None):
+    """Seeded test sample of one domain: centre cells and their 26 neighbours.
+
+    ``lit`` (optional bool per cell, e.g. a previous sweep's F > 0) steers the
+    draw towards ionisation fronts: a third of the centres are lit cells with
+    an unlit neighbour, a third lit cells, the rest uniform over the domain.
+    Returns (centres [m], neighbours [m, 26] with -1 outside, targets = the
+    sorted union of both)."""
+    n = dom.n_cells()
+    picks = []
+    if lit is not None and lit.any():
+        lit_idx = np.nonzero(lit)[0]
+        cand = lit_idx if lit_idx.size <= 200_000 else rng.choice(lit_idx, 200_000, replace=False)
+        nb = cell_neighbours(dom, cand)
+        edge = cand[np.any((nb >= 0) & ~lit[np.maximum(nb, 0)], axis=1)]
+        k = n_centres // 3
+        if edge.size:
+            picks.append(rng.choice(edge, min(k, edge.size), replace=False))
+        picks.append(rng.choice(lit_idx, min(k, lit_idx.size), replace=False))
+    rest = n_centres - sum(p.size for p in picks)
+    picks.append(rng.choice(n, min(max(rest, 0), n), replace=False))
+    centres = np.unique(np.concatenate(picks)).astype(np.int64)
+    nbs = cell_neighbours(dom, centres)
+    targets = np.unique(np.concatenate([centres, nbs[nbs >= 0]])).astype(np.int64)
+    return centres, nbs, targets
 
 
 def cell_centres_pc(dom: Domain, origin_pc=(0.0, 0.0, 0.0)) -> np.ndarray:
