@@ -200,7 +200,31 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out);
 /* Waits for the context's stream and reports device-side errors. */
 tr_status tr_sync(tr_ctx *c);
 
+/* Message of the last failed call on c; c = NULL: of the last failed call
+ * without a context (tr_delta_noalloc) on the calling thread. */
 const char *tr_last_error(const tr_ctx *c);
+
+/* delta_cell per domain without a context and without allocating, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The same result as
+ * tr_delta for the same cells (eq. delta:er:cell, lower median of f_old per
+ * domain).
+ *  - f_new_dev, f_old_dev: device arrays of dom_offsets[n_domains] cells;
+ *    domain d holds cells [dom_offsets[d], dom_offsets[d+1]).
+ *  - dom_offsets: host array of n_domains + 1 strictly increasing entries,
+ *    dom_offsets[0] = 0 (every domain non-empty).
+ *  - n_domains: 1 .. 64 (TR_EINVAL beyond: the library's static scratch holds
+ *    the radix-select state of 64 domains, about 67 KB per device, kept
+ *    until the process ends).
+ *  - delta_dev: device array of n_domains doubles (caller-owned), written
+ *    asynchronously on hip_stream (NULL: the default stream).
+ * Launches kernels only (no allocation, no memset, no host synchronisation),
+ * so it may be captured.  All calls on one device share that scratch: calls
+ * whose work overlaps on one device (other streams, other threads) race and
+ * must be ordered by the caller.  Errors: TR_EINVAL / TR_EHIP with the
+ * message in tr_last_error(NULL) of the calling thread. */
+tr_status tr_delta_noalloc(const double *f_new_dev, const double *f_old_dev, const int64_t *dom_offsets,
+                           int32_t n_domains, double *delta_dev, void *hip_stream);
 
 /* Digest of the sources the library was built from (16 hex digits; a static
  * string, never NULL).  Bindings compare it with the sources they ship with

@@ -21,7 +21,7 @@ TR_FP64, TR_FP32C = 0, 1
 # every entry point of include/treeray.h
 SYMBOLS = ["tr_create", "tr_set_domains", "tr_cell_count", "tr_set_sources", "tr_build", "tr_sweep",
            "tr_sweep_targets", "tr_delta", "tr_step", "tr_solve", "tr_set_precision", "tr_set_launch", "tr_autotune",
-           "tr_get_stats", "tr_sync", "tr_last_error", "tr_destroy", "tr_source_digest"]
+           "tr_get_stats", "tr_sync", "tr_last_error", "tr_destroy", "tr_source_digest", "tr_delta_noalloc"]
 
 
 class TreeRayError(RuntimeError):
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "tr_last_error": ([vp], C.c_char_p),
         "tr_destroy": ([vp], None),
         "tr_source_digest": ([], C.c_char_p),
+        "tr_delta_noalloc": ([vp, vp, i64p, C.c_int32, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -97,6 +98,21 @@ def load_library(path: str = LIB_PATH):
         f.restype = res
     _lib = L
     return L
+
+
+def delta_noalloc(f_new, f_old, dom_offsets, delta_out, stream=None):
+    """tr_delta_noalloc: delta_cell per domain into the device tensor delta_out
+    (float64 [n_domains]) without a context or an allocation; dom_offsets are
+    the n_domains + 1 cell offsets (host)."""
+    import torch
+    L = load_library()
+    off = np.ascontiguousarray(dom_offsets, dtype=np.int64)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = L.tr_delta_noalloc(_ptr(f_new), _ptr(f_old), off.ctypes.data_as(C.POINTER(C.c_int64)), len(off) - 1,
+                            _ptr(delta_out), C.c_void_p(st.cuda_stream))
+    if rc != TR_OK:
+        msg = L.tr_last_error(None)
+        raise TreeRayError(rc, msg.decode() if msg else "")
 
 
 def _ptr(t):

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1601,19 +1602,43 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_cas_fallback(SweepArgs 
 // previous flux, found exactly by an 8-pass radix select over the IEEE bit
 // patterns (non-negative doubles order like their bits).
 // ---------------------------------------------------------------------------
-__global__ void k_hist(int64_t n_cells, const double *__restrict__ f, const int32_t *__restrict__ cell_dom,
+// The domain of a cell: from the per-cell array of a context, or from the
+// cell ranges of at most kStaticDomains domains (the entry point without a
+// context), found by bisection.
+constexpr int kStaticDomains = 64;
+struct DomByArray {
+    const int32_t *cell_dom;
+    __device__ int operator()(int64_t c) const { return cell_dom[c]; }
+};
+struct DomByRanges {
+    int32_t n;
+    int64_t off[kStaticDomains + 1];   // domain d holds cells [off[d], off[d+1])
+    __device__ int operator()(int64_t c) const
+    {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
+};
+
+template <typename DomOf>
+__global__ void k_hist(int64_t n_cells, const double *__restrict__ f, DomOf dom_of,
                        const unsigned long long *__restrict__ prefix, int shift, unsigned int *__restrict__ hist)
 {
     __shared__ unsigned int h[256];
     const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t c = b0 + threadIdx.x;
     const int64_t last = (b0 + blockDim.x - 1 < n_cells ? b0 + blockDim.x - 1 : n_cells - 1);
-    const int dom0 = cell_dom[b0], dom1 = cell_dom[last];
+    const int dom0 = dom_of(b0), dom1 = dom_of(last);
     const bool one = dom0 == dom1;   // whole block in one domain: count in LDS first
     for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
     __syncthreads();
     if (c < n_cells) {
-        const int dom = cell_dom[c];
+        const int dom = dom_of(c);
         const unsigned long long key = (unsigned long long)__double_as_longlong(f[c]);
         const unsigned long long mask = (shift >= 56) ? 0ull : (~0ull << (shift + 8));
         if ((key & mask) == prefix[dom]) {
@@ -1657,20 +1682,31 @@ __global__ void k_rank_init(int n_dom, const DomDev *__restrict__ doms, unsigned
     dmax[d] = 0ull;
 }
 
+__global__ void k_rank_init_ranges(DomByRanges R, unsigned long long *rank, unsigned long long *prefix,
+                                   unsigned long long *dmax)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= R.n) return;
+    rank[d] = (unsigned long long)((R.off[d + 1] - R.off[d] - 1) / 2);   // lower median
+    prefix[d] = 0ull;
+    dmax[d] = 0ull;
+}
+
+template <typename DomOf>
 __global__ void k_delta(int64_t n_cells, const double *__restrict__ fn, const double *__restrict__ fo,
-                        const int32_t *__restrict__ cell_dom, const unsigned long long *__restrict__ med,
+                        DomOf dom_of, const unsigned long long *__restrict__ med,
                         unsigned long long *__restrict__ dmax)
 {
     __shared__ unsigned long long wmax[16];
     const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t c = b0 + threadIdx.x;
     const int64_t last = (b0 + blockDim.x - 1 < n_cells ? b0 + blockDim.x - 1 : n_cells - 1);
-    const int dom0 = cell_dom[b0];
-    const bool one = dom0 == cell_dom[last];
+    const int dom0 = dom_of(b0);
+    const bool one = dom0 == dom_of(last);
     unsigned long long key = 0;   // bits of a non-negative double order like the value
     int dom = dom0;
     if (c < n_cells) {
-        dom = cell_dom[c];
+        dom = dom_of(c);
         const double m = __longlong_as_double((long long)med[dom]);
         const double old = fo[c];
         const double norm = old > m ? old : m;
@@ -1697,6 +1733,20 @@ __global__ void k_delta(int64_t n_cells, const double *__restrict__ fn, const do
         atomicMax(&dmax[dom0], mx);
     }
 }
+
+// the per-domain maxima (bit patterns of non-negative doubles) as doubles
+__global__ void k_store_delta(int n_dom, const unsigned long long *__restrict__ dmax, double *__restrict__ out)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d < n_dom) out[d] = __longlong_as_double((long long)dmax[d]);
+}
+
+// Scratch of the entry point without allocation (tr_delta_noalloc): per
+// domain a 256-bin histogram, the median's bit prefix, the rank still to
+// skip and the running maximum.  One copy per device, held until the
+// process ends; every call on a device shares it.
+constexpr size_t kStaticScratchWords = (size_t)kStaticDomains * 128 + 3 * kStaticDomains;
+static __device__ __align__(256) unsigned long long scratch[kStaticScratchWords];
 
 }  // namespace tr
 
@@ -2201,6 +2251,35 @@ tr_status read_flags(tr_ctx *c)
     return TR_OK;
 }
 
+// Device address of the static scratch, resolved once per device with that
+// device current (the array's host-side name is only a stand-in for it).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// message of the last call made without a context, per thread
+thread_local std::string g_free_err;
+
+tr_status fail_free(tr_status s, const std::string &m)
+{
+    g_free_err = m;
+    return s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2228,6 +2307,11 @@ tr_status tr_create(tr_ctx **out, const tr_params *p, void *stream)
         return TR_EHIP;
     }
     c->n_cu = prop.multiProcessorCount;
+    void *sp = nullptr;
+    if (static_scratch(c->device, &sp) != hipSuccess) {   // resolved here, outside any capture
+        delete c;
+        return TR_EHIP;
+    }
     if (hipMalloc((void **)&c->queue, 64) != hipSuccess || hipMalloc((void **)&c->stats, 64) != hipSuccess ||
         hipMalloc((void **)&c->err_flags, 64) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess) {
@@ -2264,7 +2348,7 @@ void tr_destroy(tr_ctx *c)
     delete c;
 }
 
-const char *tr_last_error(const tr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+const char *tr_last_error(const tr_ctx *c) { return c ? c->err.c_str() : g_free_err.c_str(); }
 
 tr_status tr_set_domains(tr_ctx *c, int32_t n_domains, const tr_domain *doms)
 {
@@ -2465,13 +2549,14 @@ tr_status enqueue_delta(tr_ctx *c, const double *f_new, const double *f_old)
                        c->dmax);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid1(256 * nd)), dim3(256), 0, c->stream, (int32_t *)c->hist,
                        (int64_t)256 * nd, 0);
+    const DomByArray by{c->cell_dom};
     for (int shift = 56; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_hist, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_old, c->cell_dom, c->dprefix,
-                           shift, c->hist);
+        hipLaunchKernelGGL(k_hist<DomByArray>, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_old, by,
+                           c->dprefix, shift, c->hist);
         hipLaunchKernelGGL(k_select, dim3(grid1(nd, 64)), dim3(64), 0, c->stream, nd, shift, c->hist, c->dprefix,
                            c->drank);
     }
-    hipLaunchKernelGGL(k_delta, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_new, f_old, c->cell_dom,
+    hipLaunchKernelGGL(k_delta<DomByArray>, dim3(grid1(ncell)), dim3(256), 0, c->stream, ncell, f_new, f_old, by,
                        c->dprefix, c->dmax);
     HIPCHK(hipGetLastError());
     return TR_OK;
@@ -2781,6 +2866,49 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
     float ms = 0;
     if (c->timed_valid && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) out->last_sweep_ms = ms;
     (void)hipGetLastError();
+    return TR_OK;
+}
+
+tr_status tr_delta_noalloc(const double *f_new, const double *f_old, const int64_t *dom_offsets, int32_t n_domains,
+                           double *delta_dev, void *stream)
+{
+    if (!f_new || !f_old || !dom_offsets || !delta_dev) return fail_free(TR_EINVAL, "NULL argument");
+    if (n_domains < 1 || n_domains > kStaticDomains)
+        return fail_free(TR_EINVAL, "n_domains must be in [1, " + std::to_string(kStaticDomains) +
+                                        "]: the static scratch holds " + std::to_string(kStaticDomains) + " domains");
+    DomByRanges R{};
+    R.n = n_domains;
+    if (dom_offsets[0] != 0) return fail_free(TR_EINVAL, "dom_offsets[0] must be 0");
+    for (int d = 0; d <= n_domains; ++d) {
+        R.off[d] = dom_offsets[d];
+        if (d > 0 && dom_offsets[d] <= dom_offsets[d - 1])
+            return fail_free(TR_EINVAL, "every domain needs at least one cell (dom_offsets strictly increasing)");
+    }
+    const int64_t ncell = R.off[n_domains];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail_free(TR_EHIP, "hipGetDevice failed");
+    void *sp = nullptr;
+    const hipError_t e = static_scratch(dev, &sp);
+    if (e != hipSuccess) return fail_free(TR_EHIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    unsigned int *hist = (unsigned int *)sp;
+    unsigned long long *prefix = (unsigned long long *)sp + (size_t)kStaticDomains * 128;
+    unsigned long long *rank = prefix + kStaticDomains, *dmax = rank + kStaticDomains;
+    hipStream_t st = (hipStream_t)stream;
+    const int nd = n_domains;
+    (void)hipGetLastError();
+    // the last call's contents stay in the scratch: everything read is set here first
+    hipLaunchKernelGGL(k_rank_init_ranges, dim3(1), dim3(64), 0, st, R, rank, prefix, dmax);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(256 * nd)), dim3(256), 0, st, (int32_t *)hist, (int64_t)256 * nd, 0);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_hist<DomByRanges>, dim3(grid1(ncell)), dim3(256), 0, st, ncell, f_old, R, prefix, shift,
+                           hist);
+        hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, st, nd, shift, hist, prefix, rank);
+    }
+    hipLaunchKernelGGL(k_delta<DomByRanges>, dim3(grid1(ncell)), dim3(256), 0, st, ncell, f_new, f_old, R, prefix,
+                       dmax);
+    hipLaunchKernelGGL(k_store_delta, dim3(1), dim3(64), 0, st, nd, dmax, delta_dev);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return fail_free(TR_EHIP, std::string("launch failed: ") + hipGetErrorString(le));
     return TR_OK;
 }
 
