@@ -55,6 +55,7 @@ VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 FLOP_SUBPOINT, FLOP_RADIAL, FLOP_ACCUM = 40, 80, 60
 NODE_BYTES = {"f32": 32, "f64": 60}
 # lanes per ray reported by the library -> the integration code of tr_set_launch
+# (+3 when the rays were marched in FP32)
 INT_MODE = {1: 1, 64: 2, 4: 3, 8: 4, 16: 5}
 
 
@@ -211,9 +212,10 @@ def main():
         res = dict(ms_per_step=dt * 1e3, value=n_cells * npix / dt, sweep_ms=float(np.mean(sweep_ms)),
                    steps=steps, warmup=warmup, accepted=int(acc), tested=int(tested), guard=int(guard),
                    waves=st.waves_per_target, per_cu=st.targets_per_cu, lds=st.buffer_in_lds,
-                   nr=st.n_radial_max, intw=st.integration_wave, cas=st.lds_cas)
-        res["launch"] = (f"{res['waves']},{res['per_cu']},{1 if res['lds'] else 2},{INT_MODE[res['intw']]},"
-                         f"{2 if res['cas'] else 1}")
+                   nr=st.n_radial_max, intw=st.integration_wave, cas=st.lds_cas, int32=st.integration_fp32,
+                   rays32=st.rays_fp32, rays64=st.rays_fp64_again, tab=st.nodes_tabulated)
+        im = INT_MODE[res["intw"]] + (3 if res["int32"] else 0)
+        res["launch"] = f"{res['waves']},{res['per_cu']},{1 if res['lds'] else 2},{im},{2 if res['cas'] else 1}"
         log(f"{name}: {res['ms_per_step']:.2f} ms/step, sweep {res['sweep_ms']:.2f} ms, launch {res['launch']}")
         # the same outer iteration as one hipGraph launch, ping-ponging two flux buffers
         if graph_steps > 0:
@@ -302,7 +304,9 @@ def main():
                    "n_sources": int(sum(len(q) for q in P.src_q)),
                    "theta": P.params.theta, "theta_if": P.params.theta_if, "theta_src": P.params.theta_src,
                    "n_radial_max": r["nr"],
-                   "precision": ("FP32 walk/weights/ray buffers, FP64 moments, ray integration and flux sums"
+                   "precision": (("FP32 walk/weights/ray buffers, FP64 moments; FP32 ray march with compensated "
+                                  "Phi and flux sums, FP64 again near ionisation fronts" if r["int32"] else
+                                  "FP32 walk/weights/ray buffers, FP64 moments, ray integration and flux sums")
                                  if main_form == "f32" else "FP64 throughout")},
         "sweep_ms": round(r["sweep_ms"], 3),
         "ms_per_step_graph": round(r.get("ms_per_step_graph", float("nan")), 3),
@@ -310,6 +314,8 @@ def main():
         "nodes_accepted_per_target": round(r["accepted"] / n_cells, 1),
         "nodes_tested_per_target": round(r["tested"] / n_cells, 1),
         "guard_recomputes_per_accepted_node": round(r["guard"] / max(1, r["accepted"]), 4),
+        "rays_marched_fp32": r["rays32"], "rays_marched_again_fp64": r["rays64"],
+        "nodes_from_angular_table": round(r["tab"] / max(1, r["accepted"]), 4),
         "roofline": roof,
         "roofline_other": other,
     }

@@ -52,9 +52,10 @@ typedef enum {
 typedef enum {
     TR_FP64 = 0,        /* FP64 throughout */
     TR_FP32C = 1        /* FP32 walk, angular and radial weights and ray buffers;
-                           FP64 node moments, FP64 ray integration and FP64
-                           flux sums (which stand in for compensated FP32
-                           sums: FP64 vector math runs at the FP32 rate) */
+                           FP64 node moments.  The ray march runs in FP64 or
+                           (integration 6-8 of tr_set_launch, or as tuned) in
+                           FP32 with compensated sums, in FP64 again near an
+                           ionisation front (Sec. 2.5) */
 } tr_precision;
 
 /* One grid: an array of nroot root blocks of 8^3 cells, optionally refined
@@ -109,7 +110,13 @@ typedef struct {
     int32_t overflow;           /* nonzero if a walk list overflowed */
     int32_t integration_wave;   /* lanes that integrated one ray in the last sweep: 1, 4, 8, 16 or 64 */
     int32_t lds_cas;            /* 1 if the last sweep accumulated its LDS ray buffers by compare-and-swap */
+    int32_t integration_fp32;   /* 1 if the last sweep marched its rays in FP32 (FP64 again near a front) */
     double last_sweep_ms;       /* device time of the last walk/map/integrate launch */
+    int64_t rays_fp32;          /* rays of the last sweep marched in FP32 */
+    int64_t rays_fp64_again;    /* of those, rays marched again in FP64 (a source below 1e-2 of its
+                                   emitted Phi, or a close call between dying and surviving) */
+    int64_t nodes_tabulated;    /* accepted nodes of the last sweep whose angular weights came from the
+                                   context's table instead of their sub-points (same values) */
 } tr_stats;
 
 /* Creates a context on the current HIP device; stream may be NULL (default
@@ -182,7 +189,10 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec);
  * rays are integrated (0 = tuned or default, 1 = a lane per ray, 2 = a wave
  * per ray with the ray's points on the lanes, 3, 4, 5 = a group of 4, 8, 16
  * lanes per ray with the ray's emitting points on the lanes, the default; a
- * ray with more emitting points than that takes a wave) and how the waves
+ * ray with more emitting points than that takes a wave; 6, 7, 8 = the same
+ * groups marching in FP32 with a compensated Phi and compensated flux sums,
+ * every ray where a source falls below 1e-2 of its emitted Phi marched again
+ * in FP64 (Sec. 2.5; FP32C only, the FP64 form takes 3, 4, 5) and how the waves
  * of a target accumulate into a shared FP32 buffer in LDS at 8 or 16 waves
  * (0 = tuned or default, compare-and-swap; 1 = hardware atomic
  * adds; 2 = compare-and-swap loops on the values' bits; elsewhere hardware

@@ -909,6 +909,7 @@ typedef struct {
     const grid_t *g;
     const orc_params *p;
     double xt[3];          /* target centre, finest units */
+    int64_t t2[3];         /* twice the target centre (an integer) */
     int64_t target;        /* target cell */
     int64_t *acc;          /* accepted node ids */
     int64_t nacc, capacc;
@@ -1020,12 +1021,15 @@ typedef struct {
 } tbuf_t;
 
 /* Angular weights of one node (Sec. 2.3): the s^3 sub-box midpoints of the
- * box with lower corner base and extent ext (finest units, base already
- * moved to the copy in use) are classified by the HEALPix pixel of their
- * direction from xt; returns the number of distinct pixels, listed in pl with
- * their sub-point counts in pc. */
-static int node_pixels(int32_t nside, int s, const double base[3], const double ext[3], const double xt[3],
-                       int64_t *pl, int *pc)
+ * box of extent ext whose lower corner lies rel2/2 from the target centre
+ * (finest units; rel2 = twice the corner minus twice the centre, an exact
+ * integer, the box already moved to the copy in use) are classified by the
+ * HEALPix pixel of their direction from the target; returns the number of
+ * distinct pixels, listed in pl with their sub-point counts in pc.  The
+ * direction is the exact offset rel2/2 plus the sub-box fraction, one
+ * rounding each, so it depends on the offset alone and not on where the
+ * target lies in the domain. */
+static int node_pixels(int32_t nside, int s, const int64_t rel2[3], const double ext[3], int64_t *pl, int *pc)
 {
     int npl = 0;
     for (int ia = 0; ia < s; ++ia)
@@ -1033,10 +1037,8 @@ static int node_pixels(int32_t nside, int s, const double base[3], const double 
             for (int ic = 0; ic < s; ++ic) {
                 int ii[3] = {ia, ib, ic};
                 double v[3];
-                for (int a = 0; a < 3; ++a) {
-                    double pa = base[a] + (((double)ii[a] + 0.5) + JIT[a]) * (ext[a] / (double)s);
-                    v[a] = pa - xt[a];
-                }
+                for (int a = 0; a < 3; ++a)
+                    v[a] = 0.5 * (double)rel2[a] + (((double)ii[a] + 0.5) + JIT[a]) * (ext[a] / (double)s);
                 int64_t pix = orc_ang2pix(nside, v[0], v[1], v[2]);
                 int found = 0;
                 for (int k = 0; k < npl; ++k)
@@ -1050,14 +1052,17 @@ int32_t orc_node_pixels(int32_t nside, int32_t s, const int64_t *olo, const int6
                         int64_t *pix_out, int32_t *count_out)
 {
     if (nside < 1 || s < 1 || s > 64) return -1;
-    int *pc = (int *)malloc(sizeof(int) * (size_t)s * s * s);
-    if (!pc) return -2;
-    double base[3], ext[3];
+    int64_t rel2[3];
+    double ext[3];
     for (int a = 0; a < 3; ++a) {
-        base[a] = (double)olo[a];
+        const double t2 = 2.0 * xt[a];   /* the target centre lies on the half-integer lattice */
+        if (t2 != floor(t2)) return -1;
+        rel2[a] = 2 * olo[a] - (int64_t)t2;
         ext[a] = (double)(ohi[a] - olo[a]);
     }
-    int n = node_pixels(nside, s, base, ext, xt, pix_out, pc);
+    int *pc = (int *)malloc(sizeof(int) * (size_t)s * s * s);
+    if (!pc) return -2;
+    int n = node_pixels(nside, s, rel2, ext, pix_out, pc);
     for (int k = 0; k < n; ++k) count_out[k] = pc[k];
     free(pc);
     return n;
@@ -1074,12 +1079,13 @@ static void map_node(const walk_t *w, const onode_t *x, const cellq_t *q_overrid
     double sh[3];
     nearest_copy(w, x, sh);
     /* angular weights */
-    double base[3], ext[3];
+    int64_t rel2[3];
+    double ext[3];
     for (int a = 0; a < 3; ++a) {
-        base[a] = (double)(x->olo[a] + sh[a]);
+        rel2[a] = 2 * (x->olo[a] + (int64_t)sh[a]) - w->t2[a];
         ext[a] = (double)(x->ohi[a] - x->olo[a]);
     }
-    int npl = node_pixels(w->p->nside, s, base, ext, w->xt, b->pl, b->pc);
+    int npl = node_pixels(w->p->nside, s, rel2, ext, b->pl, b->pc);
     /* radial weights */
     double d2 = 0;
     for (int a = 0; a < 3; ++a) {
@@ -1129,7 +1135,10 @@ static int map_target(const sweep_ctx_t *S, int64_t tc, tbuf_t *b, walk_t *w, in
     w->target = tc;
     w->nacc = 0;
     w->tested = 0;
-    for (int a = 0; a < 3; ++a) w->xt[a] = (double)g->lo[3 * tc + a] + 0.5 * (double)g->size[tc];
+    for (int a = 0; a < 3; ++a) {
+        w->xt[a] = (double)g->lo[3 * tc + a] + 0.5 * (double)g->size[tc];
+        w->t2[a] = 2 * g->lo[3 * tc + a] + g->size[tc];
+    }
     int rc = walk_node(w, 0);
     if (rc) return rc;
     for (int64_t q = 0; q < w->nacc; ++q) map_node(w, &S->t->n[w->acc[q]], NULL, nr, S->r, npix, b);
@@ -1328,7 +1337,10 @@ int64_t orc_accepted(const orc_domain *d, const orc_params *p, const double *n_h
     w.g = &P.g;
     w.p = p;
     w.target = target;
-    for (int a = 0; a < 3; ++a) w.xt[a] = (double)P.g.lo[3 * target + a] + 0.5 * (double)P.g.size[target];
+    for (int a = 0; a < 3; ++a) {
+        w.xt[a] = (double)P.g.lo[3 * target + a] + 0.5 * (double)P.g.size[target];
+        w.t2[a] = 2 * P.g.lo[3 * target + a] + P.g.size[target];
+    }
     rc = walk_node(&w, 0);
     int64_t n = rc ? rc : w.nacc;
     for (int64_t q = 0; rc == 0 && q < w.nacc && q < max_out; ++q) {

@@ -48,8 +48,9 @@ class Stats(C.Structure):
                 ("nodes_tested", C.c_int64), ("guard_recomputes", C.c_int64), ("n_radial_max", C.c_int32),
                 ("depth_max", C.c_int32), ("waves_per_target", C.c_int32), ("targets_per_cu", C.c_int32),
                 ("buffer_in_lds", C.c_int32), ("overflow", C.c_int32), ("integration_wave", C.c_int32),
-                ("lds_cas", C.c_int32),
-                ("last_sweep_ms", C.c_double)]
+                ("lds_cas", C.c_int32), ("integration_fp32", C.c_int32),
+                ("last_sweep_ms", C.c_double), ("rays_fp32", C.c_int64), ("rays_fp64_again", C.c_int64),
+                ("nodes_tabulated", C.c_int64)]
 
 
 _lib = None

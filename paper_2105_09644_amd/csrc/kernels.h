@@ -90,6 +90,52 @@ __device__ inline double group_sum(double v, int G)
     return v;
 }
 
+// The same in FP32 (one DPP move per step).
+template <int CTRL>
+__device__ inline float dpp_swap_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+__device__ inline float group_sum(float v, int G)
+{
+    v += dpp_swap_f<0xB1>(v);
+    v += dpp_swap_f<0x4E>(v);
+    if (G >= 8) v += dpp_swap_f<0x141>(v);
+    if (G >= 16) v += dpp_swap_f<0x140>(v);
+    return v;
+}
+
+// s + e = a + b exactly (Knuth's TwoSum, round to nearest)
+__device__ inline void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bv = s - a;
+    e = (a - (s - bv)) + (b - bv);
+}
+
+// Compensated group sum of (hi, lo) pairs: at each butterfly step the two
+// partial sums are added with their rounding error carried in lo; every
+// lane of a group ends with the same bits (each step adds the same two
+// values in either order, and both TwoSum and addition are commutative).
+template <int CTRL>
+__device__ inline void csum_step(float &hi, float &lo)
+{
+    const float oh = dpp_swap_f<CTRL>(hi), ol = dpp_swap_f<CTRL>(lo);
+    float s, e;
+    two_sum(hi, oh, s, e);
+    hi = s;
+    lo = (lo + ol) + e;
+}
+
+__device__ inline void group_csum(float &hi, float &lo, int G)
+{
+    csum_step<0xB1>(hi, lo);
+    csum_step<0x4E>(hi, lo);
+    if (G >= 8) csum_step<0x141>(hi, lo);
+    if (G >= 16) csum_step<0x140>(hi, lo);
+}
+
 // Exclusive prefix sum over the 64 lanes with DPP (no LDS): an inclusive
 // scan inside each row of 16 (row_shr 1, 2, 4, 8 with zeros shifted in), then
 // the row totals carried by the row broadcasts of lanes 15 and 31.
@@ -162,18 +208,21 @@ __device__ __attribute__((noinline)) int ang2pix_d(int ns, double x, double y, d
     return pix_polar(ns, ir, (int)floor(t * (double)ir), zc > 0);
 }
 
-// FP64 position of sub-point (ia, ib, ic) relative to the target: box lower
-// corner + (index + 1/2 + jitter) * box extent / s - target centre, without
-// contraction (the same operation sequence in every FP64 evaluation).
+// FP64 position of sub-point (ia, ib, ic) relative to the target: the box's
+// lower corner relative to the target centre, an exact half-integer
+// (2 corner - 2 centre is an integer), plus (index + 1/2 + jitter) * box
+// extent / s, without contraction (the same operation sequence in every FP64
+// evaluation).  It depends on the offset alone, not on where the target lies,
+// and scales exactly with the cell size.
 __device__ __attribute__((noinline)) int subpoint_pix_d(int ns, int s, int bx, int by, int bz, int ex, int ey, int ez,
                                                         int tx2, int ty2, int tz2, int ia, int ib, int ic)
 {
 #pragma clang fp contract(off)
     const double ds = (double)s;
-    const double px = (double)bx + (((double)ia + 0.5) + kJit0) * ((double)ex / ds);
-    const double py = (double)by + (((double)ib + 0.5) + kJit1) * ((double)ey / ds);
-    const double pz = (double)bz + (((double)ic + 0.5) + kJit2) * ((double)ez / ds);
-    return ang2pix_d(ns, px - 0.5 * (double)tx2, py - 0.5 * (double)ty2, pz - 0.5 * (double)tz2);
+    const double vx = 0.5 * (double)(2 * bx - tx2) + (((double)ia + 0.5) + kJit0) * ((double)ex / ds);
+    const double vy = 0.5 * (double)(2 * by - ty2) + (((double)ib + 0.5) + kJit1) * ((double)ey / ds);
+    const double vz = 0.5 * (double)(2 * bz - tz2) + (((double)ic + 0.5) + kJit2) * ((double)ez / ds);
+    return ang2pix_d(ns, vx, vy, vz);
 }
 
 // t = atan2(y, x) / (pi/2) in [0, 4].  atan(q) (2/pi) on [0, 1] is the odd

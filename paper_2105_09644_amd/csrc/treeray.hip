@@ -346,7 +346,8 @@ struct SweepArgs {
     double *f_out;
     uint8_t *ion_out;
     int32_t *queue;          // [0] next item, [1] overflow flag
-    unsigned long long *stats;  // [0] accepted, [1] tested, [2] guard recomputes
+    unsigned long long *stats;  // [0] accepted, [1] tested, [2] guard recomputes, [3] rays marched in
+                                // FP32, [4] of those marched again in FP64, [5] nodes from the table
     void *gbuf;              // ray buffers in global memory (when they do not fit in LDS)
     void *ebuf;              // split LDS buffers: the emission rows, npix x nr_max per workgroup
     int32_t split;           // 1: A, E, V rows in LDS (stride_k = 3 nr_max + 1), emission rows in ebuf
@@ -355,6 +356,8 @@ struct SweepArgs {
     int32_t nside, npix, subsample, fmax, amax, nr_max, stride_k, zeta_g;
     int32_t int_wave;        // 1: a wave per ray (lanes = points); 0: a lane per ray
     int32_t int_group;       // > 0: a group of this many lanes per ray (slots = emitting points)
+    int32_t int_fp32;        // 1 (FP32 buffers, groups): the FP32 march, FP64 again near a front
+    float front_ratio;       // Phi / Phi_jj below which the FP32 march defers a ray to FP64
     int32_t eps_kernel;      // emission kernel (K_F1 .. K_G; 0 or K_F3: two-point W_f,3)
     int32_t periodic;        // 1: every node through its periodic copy closest to the target
     int32_t mass_gauss;      // 1: W_g for A, E, V and the self term; 0: W_p
@@ -365,6 +368,14 @@ struct SweepArgs {
     int64_t ovf_cap;
     int32_t *glist;
     int32_t gfmax, gamax;
+    // angular-weight table (NULL: none): for a node of 1, 2 or 4 times the
+    // target's size (ri = 0, 1, 2) at offset o in target sizes from the
+    // target's lower corner, |o_a| <= atab_w[ri], the entry
+    // atab_idx[atab_base[ri] + ((o_x + w)(2w + 1) + o_y + w)(2w + 1) + o_z + w]
+    // = (first pair << 7) | pairs, each pair in atab_pool = pixel | count << 16
+    const int32_t *atab_idx;
+    const int32_t *atab_pool;
+    int32_t atab_w[3], atab_base[3];
 };
 
 // ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
@@ -781,6 +792,130 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
     return group_sum(live ? ph * drcp(rj * rj) : 0.0, G);
 }
 
+// The same march in FP32 (FP32C integration, Sec. 2.5), a group of G lanes
+// per ray as above, for FP32 ray buffers:
+//  - radial differences from exact integers: r_j - r_i = c (j^2 - i^2), so a
+//    segment's volume dV_{i,j} carries no cancellation error;
+//  - Phi_j is kept as an unevaluated FP32 pair (hi + lo): each loss R is
+//    subtracted by TwoSum, so Phi's error is only that of the R's themselves
+//    (a few ulp of each, at most a few 1e-7 of the emitted Phi_jj in all);
+//  - F_{0,k} = sum_j Phi_{0,j} / r_j^2 as a compensated group sum.
+// Where the FP32 result is not safe to 1e-4 -- a live source whose Phi falls
+// below front_ratio of its emitted Phi_jj, or dies in a step whose loss is
+// within 1e-3 of what it had (a close call between dying and surviving), the
+// regime of an ionisation front -- near is set on the group and the caller
+// integrates that ray again in FP64.  Returns F_{0,k} as (hi, lo) on every
+// lane of the group.  Call with every lane active.
+__device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, int tp, bool has_ray, int tmax,
+                                         float rcoef, const double *inv2r, int nr, int nside, int zeta_g,
+                                         float front_ratio, bool &ovf, bool &near, float &f_hi, float &f_lo)
+{
+    const int lane = lane_id();
+    const int sl = lane & (G - 1);
+    const int g0 = lane - sl;
+    const uint32_t gmask = (uint32_t)((1ull << G) - 1ull);
+    const float inv4pi = (float)(1.0 / (4.0 * kPi));
+    const float ns = (float)nside;
+    const float third = 1.0f / 3.0f;
+    int j = -1, cnt = 0;
+    for (int c0 = 1; c0 <= tmax; c0 += G) {
+        const int i = c0 + sl;
+        const bool em = has_ray && i <= tp && R.eps(k, i) > 0.0f;
+        const uint32_t gm = (uint32_t)(__ballot(em) >> g0) & gmask;
+        const int rank = sl - cnt;
+        if (rank >= 0 && rank < __popc(gm)) {
+            uint32_t x = gm;
+            for (int t = 0; t < rank; ++t) x &= x - 1u;
+            j = c0 + __ffs(x) - 1;
+        }
+        cnt += __popc(gm);
+    }
+    ovf = has_ray && cnt > G;
+    const bool act = has_ray && !ovf;
+    float i2rj = 0.0f, epsj = 0.0f, rj = 0.0f;
+    const int j2 = j > 0 ? j * j : 0;
+    if (act && j > 0) {
+        i2rj = (float)inv2r[j];
+        epsj = R.eps(k, j);
+        rj = rcoef * (float)j2;
+    }
+    float ph = 0.0f, pl = 0.0f, ph0 = 0.0f, a1 = 0.0f, fb1 = 0.0f;
+    bool live = false, flag = false;
+    float nV = 0.0f, nA = 0.0f, nE = 0.0f;
+    if (act && tmax <= tp) {
+        nV = R.V(k, tmax);
+        nA = R.A(k, tmax);
+        nE = R.E(k, tmax);
+    }
+    for (int i = tmax; i >= 0; --i) {
+        const float Vi = nV, Ai = nA, Ei = nE;
+        if (act && i >= 1 && i - 1 <= tp) {
+            nV = R.V(k, i - 1);
+            nA = R.A(k, i - 1);
+            nE = R.E(k, i - 1);
+        }
+        float ai = 0.0f, fbi = 0.0f;
+        if (Vi > 0.0f) {
+            const float rv = __builtin_amdgcn_rcpf(Vi);
+            ai = Ai * rv;
+            fbi = Ei * rv;
+        }
+        if (i <= nr - 2) {
+            const int i1sq = (i + 1) * (i + 1);
+            float f = 0.0f, B = 0.0f;
+            if (live && j >= i + 2) {
+                B = rcoef * (float)(j2 - i1sq);
+                f = (ph + pl) * __builtin_amdgcn_rcpf(B * B);
+            }
+            const float ftot = group_sum(f, G);   // F_{i+1} of the group's ray
+            float g = 0.0f;
+            if (ftot > 0.0f) {
+                g = 2.0f * __builtin_amdgcn_rcpf(ftot);
+                if (fb1 > 0.0f) g = fminf(g, __builtin_amdgcn_rcpf(fb1));
+            }
+            const float aseg = 0.5f * (ai + a1) * (rcoef * (float)(2 * i + 1)) * third;
+            if (live) {
+                const float A = rcoef * (float)(j2 - i * i);
+                if (j < i + 2) B = rcoef * (float)(j2 - i1sq);
+                float z = j >= i + 2 ? f * g : 1.0f;
+                if (zeta_g) z *= fminf(1.0f, ns * A * i2rj);
+                const float loss = aseg * (A * A + A * B + B * B) * z;
+                const float before = ph + pl;
+                float sh, se;
+                two_sum(ph, -loss, sh, se);
+                ph = sh;
+                pl += se;
+                const float after = ph + pl;
+                if (after > 0.0f) {
+                    flag |= after < front_ratio * ph0;
+                } else {
+                    flag |= loss < 1.001f * before;   // a close call: decide it in FP64
+                    ph = pl = 0.0f;
+                    live = false;
+                }
+            }
+        }
+        if (act && i >= 1 && j == i) {
+            ph = epsj * inv4pi;
+            pl = 0.0f;
+            ph0 = ph;
+            live = true;
+        }
+        a1 = ai;
+        fb1 = fbi;
+    }
+    float th = 0.0f, tl = 0.0f;
+    if (live) {
+        const float rr = __builtin_amdgcn_rcpf(rj * rj);
+        th = ph * rr;
+        tl = pl * rr;
+    }
+    group_csum(th, tl, G);
+    f_hi = th;
+    f_lo = tl;
+    near = ((uint32_t)(__ballot(flag) >> g0) & gmask) != 0u;
+}
+
 template <typename T>
 __device__ inline T rdlane(T v, int l)
 {
@@ -879,7 +1014,8 @@ __device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, 
 template <typename Real, int ATOMIC, bool KV>
 __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, const int *per, const Real *rt, int nr,
                           Real rc_inv,
-                          Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, double &guard_count)
+                          Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, int tsize, double &guard_count,
+                          double &tab_count)
 {
     using R4 = typename R4T<Real>::T;
     // emission rows (few writes; in device memory when the A, E, V rows alone fill LDS): hardware atomics
@@ -893,6 +1029,7 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
     // 2 a smoothing kernel scaled by ea, 3 the mass fall-back weights; etop: outermost point
     int emode = 0, le = 0, ne = 0, etop = 1;
     Real ea = 0, eb = 0, qeps = 0;
+    int tab = -1;   // the node's angular-table entry (-1: classify its sub-points)
     const bool mg = KV && a.mass_gauss != 0;
     if (lane < cnt) {
         const int n = acc[lane];
@@ -916,6 +1053,18 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
             bx += shx;
             by += shy;
             bz += shz;
+        }
+        if (a.atab_idx && !(g.w & kPartialBit)) {
+            // a cube of 1, 2 or 4 target sizes: offsets of its corner in target sizes (exact)
+            const int ri = size == tsize ? 0 : (size == 2 * tsize ? 1 : (size == 4 * tsize ? 2 : -1));
+            if (ri >= 0) {
+                const int sh = __builtin_ctz((unsigned)tsize);
+                const int kx = (bx - ((tx - tsize) >> 1)) >> sh, ky = (by - ((ty - tsize) >> 1)) >> sh,
+                          kz = (bz - ((tz - tsize) >> 1)) >> sh;
+                const int w = a.atab_w[ri], nw = 2 * w + 1;
+                if (abs(kx) <= w && abs(ky) <= w && abs(kz) <= w)
+                    tab = a.atab_idx[a.atab_base[ri] + ((kx + w) * nw + (ky + w)) * nw + (kz + w)];
+            }
         }
         const Real dxc = (A.x + (Real)shx) - (Real)0.5 * (Real)tx, dyc = (A.y + (Real)shy) - (Real)0.5 * (Real)ty,
                    dzc = (A.z + (Real)shz) - (Real)0.5 * (Real)tz;
@@ -1001,61 +1150,100 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
     const float inv_s = 1.0f / (float)s;
     const Real inv_s3 = (Real)1 / (Real)s3;
     const uint64_t act_mask = __ballot(active);
-    const int packed = lo | (nsup << 8) | (ie << 16);   // each below 256
+    // each below 256; bit 24: the node emits (two-point emission weights e0, e1)
+    const int packed = lo | (nsup << 8) | (ie << 16) | ((e0 != (Real)0 || e1 != (Real)0) ? 1 << 24 : 0);
     const int epacked = emode | (le << 2) | (ne << 10) | (etop << 18);   // 2 + 8 + 8 + 8 bits
+    // lanes of phase 2 cover (pixel slot, support point) pairs, span points per
+    // slot: slot of a lane = (lane mx) >> 16 with mx = ceil(2^16 / span) (exact
+    // for lanes below 64 and span <= 64), G = 64 / span slots per batch
+    int divp;
+    {
+        const int span1 = nsup < 1 ? 1 : (nsup < 64 ? nsup : 64);
+        divp = ((65536 + span1 - 1) / span1) | ((64 / span1) << 17);
+    }
+    // the W_p normalisation, or (no support point: linear split) minus the
+    // bracket weight of the lower point
+    const Real wsf = wscale > (Real)0 ? wscale : -fb0;
     // per node (lane = node): sub-box origin relative to the target and sub-box steps, FP32
     const float ox = 0.5f * (float)(2 * bx - tx), oy = 0.5f * (float)(2 * by - ty), oz = 0.5f * (float)(2 * bz - tz);
     const float sx = (float)ex * inv_s, sy = (float)ey * inv_s, sz = (float)ez * inv_s;
     for (int j = 0; j < cnt; ++j) {
-        // --- angular ---
-        int pix = 0;
-        if constexpr (sizeof(Real) == 4) {
-            const float vx = fmaf(ca, rdlane(sx, j), rdlane(ox, j));
-            const float vy = fmaf(cb, rdlane(sy, j), rdlane(oy, j));
-            const float vz = fmaf(cc, rdlane(sz, j), rdlane(oz, j));
-            bool unsure = false;
-            pix = ang2pix_f(ns, vx, vy, vz, a.guard_tol, unsure);
-            unsure &= active;
-            if (__ballot(unsure)) {
+        // --- angular: slot q (lane q of slot_kc) holds the q-th distinct pixel
+        // and its sub-point count (pixel < 2^16, count <= 64), packed so that one
+        // shuffle hands a slot to the lanes that scatter it; from the table, or
+        // by classifying the node's sub-points ---
+        int nd = 0, slot_kc = 0;
+        const int jt = rdlane(tab, j);
+        if (jt >= 0) {
+            nd = jt & 127;
+            if (lane < nd) slot_kc = a.atab_pool[(jt >> 7) + lane];
+            tab_count += lane == 0 ? 1.0 : 0.0;
+        } else {
+            int pix = 0;
+            if constexpr (sizeof(Real) == 4) {
+                const float vx = fmaf(ca, rdlane(sx, j), rdlane(ox, j));
+                const float vy = fmaf(cb, rdlane(sy, j), rdlane(oy, j));
+                const float vz = fmaf(cc, rdlane(sz, j), rdlane(oz, j));
+                bool unsure = false;
+                pix = ang2pix_f(ns, vx, vy, vz, a.guard_tol, unsure);
+                unsure &= active;
+                if (__ballot(unsure)) {
+                    const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
+                    const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
+                    if (unsure) {
+                        pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
+                        guard_count += 1.0;
+                    }
+                }
+            } else {
                 const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
                 const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
-                if (unsure) {
-                    pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
-                    guard_count += 1.0;
-                }
+                if (active) pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
             }
-        } else {
-            const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
-            const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
-            if (active) pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
-        }
-        if ((unsigned)pix >= (unsigned)a.npix) {
-            // cannot happen for a finite direction: reported, never written out of bounds
-            atomicOr(&a.queue[1], 4);
-            pix = 0;
+            if ((unsigned)pix >= (unsigned)a.npix) {
+                // cannot happen for a finite direction: reported, never written out of bounds
+                atomicOr(&a.queue[1], 4);
+                pix = 0;
+            }
+            // the distinct pixels
+            uint64_t rem = act_mask;
+            while (rem) {
+                const int first = __ffsll((unsigned long long)rem) - 1;
+                const int k = __builtin_amdgcn_readlane(pix, first);
+                const uint64_t m = __ballot(pix == k) & rem;
+                rem &= ~m;
+                const int kc = k | ((int)__popcll(m) << 16);   // uniform
+                slot_kc = lane == nd ? kc : slot_kc;
+                ++nd;
+            }
         }
         // --- radial weights: this lane serves support point lo + io of batch slot po ---
         const int jpk = rdlane(packed, j);
-        const int jlo = jpk & 255, jn = (jpk >> 8) & 255, jie = jpk >> 16;
-        const Real jd = rdlane(d, j), jhinv = rdlane(hinv, j), jws = rdlane(wscale, j), jfb = rdlane(fb0, j);
+        const int jlo = jpk & 255, jn = (jpk >> 8) & 255, jie = (jpk >> 16) & 255;
+        const Real jd = rdlane(d, j), jhinv = rdlane(hinv, j), jwf = rdlane(wsf, j);
         const Real ja = rdlane(qa, j), je = rdlane(qe, j), jv = rdlane(qv, j);
-        const Real je0 = rdlane(e0, j), je1 = rdlane(e1, j);
+        Real je0 = 0, je1 = 0;
+        if ((jpk >> 24) & 1) {
+            je0 = rdlane(e0, j);
+            je1 = rdlane(e1, j);
+        }
         const int jep = KV ? rdlane(epacked, j) : 0;
         const int jemode = jep & 3, jle = (jep >> 2) & 255, jne = (jep >> 10) & 255;
         const int jetop = KV ? (jep >> 18) : (je1 != (Real)0 ? jie + 1 : jie);
         const bool has_eps = je0 != (Real)0 || je1 != (Real)0 || jemode != 0;
         const int span = jn < 64 ? jn : 64;                         // points per batch slot
-        const int G = 64 / span;                                    // pixels per batch
-        // lane / span: (lane + 1/2)/span is at least 1/128 away from an integer
-        const int po = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)span));
+        const int jdv = rdlane(divp, j);
+        const int G = jdv >> 17;                                    // pixels per batch
+        const int po = (lane * (jdv & 0x1ffff)) >> 16;              // lane / span
         const int io = lane - po * span;
         const bool lane_ok = po < G;
         Real wa = 0, we = 0, wv = 0, wq = 0;   // wq: emission spread over the support (modes 1-3)
+        const Real jfb = -jwf;                  // the bracket weight when there is no W_p support
         if (lane_ok) {
             Real w;
-            if (jws > (Real)0) {
+            if (jwf > (Real)0) {
                 const int i = jlo + io;
-                w = smooth_kernel<Real>(mg, (rcoef * (Real)(i * i) - jd) * jhinv) * jws;
+                w = smooth_kernel<Real>(mg, (rcoef * (Real)(i * i) - jd) * jhinv) * jwf;
             } else {
                 w = io == 0 ? jfb : (Real)1 - jfb;
             }
@@ -1066,21 +1254,7 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
                                                        jfb, rcoef, jd, jhinv, a.eps_kernel == K_G) *
                                   rdlane(qeps, j);
         }
-        // --- distinct pixels: slot q (lane q of slot_k / slot_c) holds pixel k_q and its count ---
-        uint64_t rem = act_mask;
-        int nd = 0, slot_k = 0, slot_c = 0;
-        while (rem) {
-            const int first = __ffsll((unsigned long long)rem) - 1;
-            const int k = __builtin_amdgcn_readlane(pix, first);
-            const uint64_t m = __ballot(pix == k) & rem;
-            rem &= ~m;
-            if (lane == nd) {
-                slot_k = k;
-                slot_c = (int)__popcll(m);
-            }
-            ++nd;
-        }
-        const int slot_kc = slot_k | (slot_c << 16);   // pixel < 2^16, count <= 64: one shuffle per batch
+        const int slot_k = slot_kc & 0xffff, slot_c = slot_kc >> 16;
         // emission: lane q deposits pixel q's share on the two bracket points
         // (the spread forms go with A, E, V below); the ray's outermost emitting point
         if (has_eps && lane < nd) {
@@ -1113,7 +1287,7 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
                 for (int i2 = 64 + lane; i2 < jn; i2 += 64) {
                     const int i = jlo + i2;
                     const Real w2 =
-                        jws > (Real)0 ? smooth_kernel<Real>(mg, (rcoef * (Real)(i * i) - jd) * jhinv) * jws : (Real)0;
+                        jwf > (Real)0 ? smooth_kernel<Real>(mg, (rcoef * (Real)(i * i) - jd) * jhinv) * jwf : (Real)0;
                     buf_add<Real, ATOMIC>(row + i2, wk * w2 * ja);
                     buf_add<Real, ATOMIC>(row + nrm + i2, wk * w2 * je);
                     buf_add<Real, ATOMIC>(row + 2 * nrm + i2, wk * w2 * jv);
@@ -1275,7 +1449,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     p += WAVES * sizeof(double);
     int *top = (int *)p;   // per ray: outermost point holding emission (0: none)
 
-    double n_acc = 0, n_test = 0, n_guard = 0;
+    double n_acc = 0, n_test = 0, n_guard = 0, n_f32 = 0, n_f64 = 0, n_tab = 0;
     const int64_t n_items =
         FALLBACK ? min((int64_t)__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
                    : a.n_items;
@@ -1414,7 +1588,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             end = uniform(end);
             if (end <= start) break;
             map_nodes<Real, ATOMIC, KV>(a, R, top, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
-                                        n_guard);
+                                        tsize, n_guard, n_tab);
         }
         __syncthreads();
         if (scb[S_OVF]) {
@@ -1441,6 +1615,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
         constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
         double fsum = 0.0;
+        float cs_hi = 0.0f, cs_lo = 0.0f;   // compensated FP32 sum of this lane's FP32-marched rays
         if (wave >= IW) {
             // no rays here
         } else if (a.int_group > 0) {
@@ -1472,10 +1647,39 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 }
                 const bool has = myk >= 0;
                 bool ovf = false;
-                const double f = integrate_rays_group<Real>(R, G, has ? myk : 0, mytp, has, tmax, rd, rd2, nr, a.nside,
-                                                            a.zeta_g, ovf);
                 const bool head = (lane & (G - 1)) == 0;
-                if (head && has && !ovf) fsum += f;
+                bool fp32_done = false;
+                if constexpr (sizeof(Real) == 4) {
+                    if (a.int_fp32) {
+                        fp32_done = true;
+                        bool near = false;
+                        float fh = 0.0f, fl = 0.0f;
+                        integrate_rays_group_f32(R, G, has ? myk : 0, mytp, has, tmax, rcoef, rd2, nr, a.nside,
+                                                 a.zeta_g, a.front_ratio, ovf, near, fh, fl);
+                        const bool ok = head && has && !ovf;
+                        if (ok && !near) {
+                            float sh, se;
+                            two_sum(cs_hi, fh, sh, se);
+                            cs_hi = sh;
+                            cs_lo += se + fl;
+                        }
+                        n_f32 += ok ? 1.0 : 0.0;
+                        // the rays near an ionisation front, again in FP64
+                        const bool redo = has && !ovf && near;
+                        if (__ballot(head && redo)) {
+                            bool ovf2 = false;
+                            const double f = integrate_rays_group<Real>(R, G, redo ? myk : 0, mytp, redo, tmax, rd,
+                                                                        rd2, nr, a.nside, a.zeta_g, ovf2);
+                            if (head && redo) fsum += f;
+                            n_f64 += head && redo ? 1.0 : 0.0;
+                        }
+                    }
+                }
+                if (!fp32_done) {
+                    const double f = integrate_rays_group<Real>(R, G, has ? myk : 0, mytp, has, tmax, rd, rd2, nr,
+                                                                a.nside, a.zeta_g, ovf);
+                    if (head && has && !ovf) fsum += f;
+                }
                 // a ray with more emitting points than the group has lanes: a wave
                 uint64_t om = __ballot(head && ovf);
                 while (om) {
@@ -1536,6 +1740,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 }
             }
         }
+        fsum += (double)cs_hi + (double)cs_lo;
         fsum = wave_sum(fsum);
         if (lane == 0) red[wave] = fsum;
         __syncthreads();
@@ -1552,10 +1757,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     // statistics
     n_test = wave_sum(n_test);
     n_guard = wave_sum(n_guard);
+    n_f32 = wave_sum(n_f32);
+    n_f64 = wave_sum(n_f64);
+    n_tab = wave_sum(n_tab);
     if (lane == 0) {
         if (wave == 0 && n_acc > 0) atomicAdd(&a.stats[0], (unsigned long long)n_acc);
         if (n_test > 0) atomicAdd(&a.stats[1], (unsigned long long)n_test);
         if (n_guard > 0) atomicAdd(&a.stats[2], (unsigned long long)n_guard);
+        if (n_f32 > 0) atomicAdd(&a.stats[3], (unsigned long long)n_f32);
+        if (n_f64 > 0) atomicAdd(&a.stats[4], (unsigned long long)n_f64);
+        if (n_tab > 0) atomicAdd(&a.stats[5], (unsigned long long)n_tab);
     }
 }
 
@@ -1602,6 +1813,75 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_cas_fallback(SweepArgs 
 // previous flux, found exactly by an 8-pass radix select over the IEEE bit
 // patterns (non-negative doubles order like their bits).
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Angular-weight table (Sec. 2.3 "Mapping nodes onto rays").  A node's
+// angular weights depend only on its box relative to the target; for nodes of
+// 1, 2 or 4 times the target's size they are tabulated once per context by
+// offset, in units of the target's size, with the FP64 classifier the sweep
+// itself uses: relative sub-point positions scale exactly with the size, so a
+// table entry holds exactly what the sweep would compute for that node.  One
+// thread per offset; first the number of distinct pixels, then (after a
+// prefix sum on the host) the pairs themselves, in the order of first
+// appearance over the sub-points.
+// ---------------------------------------------------------------------------
+struct AtabGeom {
+    int32_t w[3], base[3], nkeys;
+};
+
+__device__ inline void atab_key(const AtabGeom &G, int key, int &r, int &ox, int &oy, int &oz)
+{
+    int ri = key >= G.base[2] ? 2 : (key >= G.base[1] ? 1 : 0);
+    int k = key - G.base[ri];
+    const int w = G.w[ri], n = 2 * w + 1;
+    oz = k % n - w;
+    k /= n;
+    oy = k % n - w;
+    ox = k / n - w;
+    r = 1 << ri;
+}
+
+__device__ int atab_pairs(const AtabGeom &G, int key, int ns, int s, int *pix, int *cnt)
+{
+    int r, ox, oy, oz;
+    atab_key(G, key, r, ox, oy, oz);
+    int npl = 0;
+    for (int ia = 0; ia < s; ++ia)
+        for (int ib = 0; ib < s; ++ib)
+            for (int ic = 0; ic < s; ++ic) {
+                // a unit target with its lower corner at the origin: twice its centre is (1, 1, 1)
+                const int p = subpoint_pix_d(ns, s, ox, oy, oz, r, r, r, 1, 1, 1, ia, ib, ic);
+                int q = 0;
+                while (q < npl && pix[q] != p) ++q;
+                if (q == npl) {
+                    pix[npl] = p;
+                    cnt[npl] = 0;
+                    ++npl;
+                }
+                ++cnt[q];
+            }
+    return npl;
+}
+
+__global__ void k_atab_count(AtabGeom G, int ns, int s, int32_t *npairs)
+{
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= G.nkeys) return;
+    int pix[64], cnt[64];
+    npairs[key] = atab_pairs(G, key, ns, s, pix, cnt);
+}
+
+__global__ void k_atab_fill(AtabGeom G, int ns, int s, const int32_t *__restrict__ first, int32_t *idx,
+                            int32_t *pool)
+{
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= G.nkeys) return;
+    int pix[64], cnt[64];
+    const int n = atab_pairs(G, key, ns, s, pix, cnt);
+    const int f = first[key];
+    for (int q = 0; q < n; ++q) pool[f + q] = pix[q] | (cnt[q] << 16);
+    idx[key] = (f << 7) | n;
+}
+
 // The domain of a cell: from the per-cell array of a context, or from the
 // cell ranges of at most kStaticDomains domains (the entry point without a
 // context), found by bisection.
@@ -1796,6 +2076,9 @@ struct tr_ctx {
     int32_t *glist = nullptr;            // walk lists of the fallback pass
     int32_t *ovf = nullptr;              // items queued for it
     int64_t ovf_cap = 0;
+    // angular-weight table (built in tr_set_domains)
+    int32_t *atab_idx = nullptr, *atab_pool = nullptr;
+    AtabGeom atab{};
     // delta scratch
     unsigned int *hist = nullptr;
     unsigned long long *dprefix = nullptr, *drank = nullptr, *dmax = nullptr;
@@ -1805,7 +2088,7 @@ struct tr_ctx {
     bool built = false;
     tr_precision built_prec = TR_FP64;
     int32_t waves = 0, tpc = 0, bufmode = 0, intmode = 0, atommode = 0;   // user launch shape (0 = default)
-    int32_t last_waves = 0, last_tpc = 0, last_lds = 0, last_intw = 0, last_cas = 0;
+    int32_t last_waves = 0, last_tpc = 0, last_lds = 0, last_intw = 0, last_cas = 0, last_int32 = 0;
     int tuned_waves[2] = {0, 0};         // per precision after tr_autotune
     int tuned_buf[2] = {0, 0};
     int tuned_int[2] = {0, 0};
@@ -1869,6 +2152,7 @@ void free_domains(tr_ctx *c)
     dfree(c->r64); dfree(c->r32); dfree(c->mom); dfree(c->packA); dfree(c->packB);
     dfree(c->ndot); dfree(c->d_sxyz); dfree(c->d_sq); dfree(c->d_sdom);
     dfree(c->hist); dfree(c->dprefix); dfree(c->drank); dfree(c->dmax);
+    dfree(c->atab_idx); dfree(c->atab_pool);
     dfree(c->solve_tmp);
     dfree(c->gbuf);
     c->gbuf_bytes = 0;
@@ -1986,11 +2270,12 @@ struct LaunchPlan {
     bool ldsbuf = true;
     bool cas = false;   // FP32 LDS buffers accumulated by compare-and-swap
     bool split = false; // A, E, V rows in LDS, emission rows in device memory
-    int intm = 1;   // integration: 1 a lane per ray, 2 a wave per ray, 3/4/5 a group of 4/8/16 lanes
+    int intm = 1;   // integration: 1 a lane per ray, 2 a wave per ray, 3/4/5 a group of 4/8/16 lanes,
+                    // 6/7/8 the same groups with the FP32 march (FP32 buffers only)
 };
 
 // lanes that integrate one ray in integration mode m
-inline int lanes_per_ray(int m) { return m == 2 ? 64 : (m >= 3 ? 4 << (m - 3) : 1); }
+inline int lanes_per_ray(int m) { return m == 2 ? 64 : (m >= 3 ? 4 << ((m - 3) % 3) : 1); }
 
 tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int buf_req, int int_req, LaunchPlan &L,
                      int atom_req = 0)
@@ -2055,7 +2340,9 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     // has lanes take a wave): 16 lanes from N_side 4 on, where a ray crosses
     // more nodes, else 8
     const int im = int_req > 0 ? int_req : c->tuned_int[f32 ? 1 : 0];
-    L.intm = im > 0 ? im : (npix >= 192 ? 5 : 4);
+    // (FP32 buffers march in FP32 by default, the FP64 form in FP64)
+    L.intm = im > 0 ? im : (npix >= 192 ? 5 : 4) + (f32 ? 3 : 0);
+    if (L.intm >= 6 && !f32) L.intm -= 3;
     int64_t blocks = (int64_t)c->n_cu * L.per_cu;
     if (blocks > n_items) blocks = std::max<int64_t>(1, n_items);
     L.blocks = (int)blocks;
@@ -2146,6 +2433,8 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.zeta_g = c->p.zeta_g;
     a.int_wave = L.intm == 2 ? 1 : 0;
     a.int_group = L.intm >= 3 ? lanes_per_ray(L.intm) : 0;
+    a.int_fp32 = L.intm >= 6 ? 1 : 0;
+    a.front_ratio = 1e-2f;
     a.eps_kernel = c->p.eps_kernel;
     a.periodic = c->p.periodic ? 1 : 0;
     a.mass_gauss = c->p.mass_kernel == 6 ? 1 : 0;
@@ -2154,9 +2443,15 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.glist = c->glist;
     a.gfmax = kGlobalList;
     a.gamax = kGlobalList;
+    a.atab_idx = c->atab_idx;
+    a.atab_pool = c->atab_pool;
+    for (int q = 0; q < 3; ++q) {
+        a.atab_w[q] = c->atab.w[q];
+        a.atab_base[q] = c->atab.base[q];
+    }
     (void)hipGetLastError();   // a stale error of an earlier, unrelated call is not ours
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->queue, (int64_t)4, 0);
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, c->stats, (int64_t)4);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, c->stats, (int64_t)8);
     if (timed) HIPCHK(hipEventRecord(c->ev0, c->stream));
     hipLaunchKernelGGL(L.fn, dim3(L.blocks), dim3(L.waves * 64), L.lds, c->stream, a);
     // the targets whose walk lists did not fit in LDS, again with lists in device memory
@@ -2176,6 +2471,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     c->last_tpc = L.per_cu;
     c->last_lds = L.ldsbuf ? (L.split ? 2 : 1) : 0;
     c->last_intw = lanes_per_ray(L.intm);
+    c->last_int32 = L.intm >= 6 ? 1 : 0;
     c->last_cas = L.cas ? 1 : 0;
     return TR_OK;
 }
@@ -2237,6 +2533,62 @@ tr_status upload_gauss_legendre(tr_ctx *c)
     }
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_t), t, sizeof(t)));
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), w, sizeof(w)));
+    return TR_OK;
+}
+
+// The angular-weight table of the context's N_side and s: offsets up to
+// (2/theta + 1) r target sizes per axis for nodes of r = 1, 2, 4 target sizes
+// (every node the Barnes-Hut walk accepts at theta_lim lies inside), capped so
+// that the table stays small; nodes outside classify their sub-points.
+tr_status build_angular_table(tr_ctx *c)
+{
+    const int s = c->p.subsample, ns = c->p.nside;
+    const double th = c->p.theta > 0.05 ? c->p.theta : 0.05;
+    const int cap[3] = {12, 20, 24};
+    AtabGeom G{};
+    int64_t nk = 0;
+    for (int q = 0; q < 3; ++q) {
+        const int w = std::min(cap[q], (int)std::ceil((2.0 / th + 1.0) * (double)(1 << q)));
+        G.w[q] = w;
+        G.base[q] = (int32_t)nk;
+        nk += (int64_t)(2 * w + 1) * (2 * w + 1) * (2 * w + 1);
+    }
+    G.nkeys = (int32_t)nk;
+    int32_t *cnt = nullptr;
+    tr_status st;
+    if ((st = dalloc(c, (void **)&cnt, sizeof(int32_t) * (size_t)nk))) return st;
+    hipLaunchKernelGGL(k_atab_count, dim3(grid1(nk, 64)), dim3(64), 0, c->stream, G, ns, s, cnt);
+    std::vector<int32_t> h((size_t)nk);
+    if (hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * (size_t)nk, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        dfree(cnt);
+        return fail(c, TR_EHIP, "angular table: counting failed");
+    }
+    int64_t tot = 0;
+    for (auto &v : h) {
+        const int32_t n = v;
+        v = (int32_t)tot;   // first pair of each entry
+        tot += n;
+    }
+    if (tot >= (1ll << 24)) {   // (first << 7) | pairs must fit an int: keep classifying instead
+        dfree(cnt);
+        return TR_OK;
+    }
+    if ((st = dalloc(c, (void **)&c->atab_pool, sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1))) ||
+        (st = dalloc(c, (void **)&c->atab_idx, sizeof(int32_t) * (size_t)nk))) {
+        dfree(cnt);
+        return st;
+    }
+    if (hipMemcpyAsync(cnt, h.data(), sizeof(int32_t) * (size_t)nk, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+        dfree(cnt);
+        return fail(c, TR_EHIP, "angular table: upload failed");
+    }
+    hipLaunchKernelGGL(k_atab_fill, dim3(grid1(nk, 64)), dim3(64), 0, c->stream, G, ns, s, cnt, c->atab_idx,
+                       c->atab_pool);
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    dfree(cnt);
+    if (e != hipSuccess) return fail(c, TR_EHIP, std::string("angular table: ") + hipGetErrorString(e));
+    c->atab = G;
     return TR_OK;
 }
 
@@ -2466,6 +2818,7 @@ tr_status tr_set_domains(tr_ctx *c, int32_t n_domains, const tr_domain *doms)
     c->sq.assign(n_domains, {});
     c->src_dirty = true;
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->p.subsample * c->p.subsample * c->p.subsample <= 64 && (s = build_angular_table(c))) return s;
     return TR_OK;
 }
 
@@ -2745,10 +3098,10 @@ tr_status tr_set_launch(tr_ctx *c, int32_t waves, int32_t tpc, int32_t buffer, i
     if (atomics < 0 || atomics > 2)
         return fail(c, TR_EINVAL, "atomics must be 0 (auto), 1 (hardware atomic adds) or 2 (compare-and-swap)");
     if (buffer < 0 || buffer > 2) return fail(c, TR_EINVAL, "buffer must be 0 (auto), 1 (LDS) or 2 (device memory)");
-    if (integration < 0 || integration > 5)
+    if (integration < 0 || integration > 8)
         return fail(c, TR_EINVAL,
-                    "integration must be 0 (auto), 1 (a lane per ray), 2 (a wave per ray) or 3, 4, 5 (a group of 4, 8, "
-                    "16 lanes per ray)");
+                    "integration must be 0 (auto), 1 (a lane per ray), 2 (a wave per ray), 3, 4, 5 (a group of 4, 8, "
+                    "16 lanes per ray) or 6, 7, 8 (the same groups with the FP32 march)");
     if (!(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16))
         return fail(c, TR_EINVAL, "waves per target must be 0, 1, 2, 4, 8 or 16");
     if (tpc < 0) return fail(c, TR_EINVAL, "targets per CU must be >= 0");
@@ -2810,7 +3163,8 @@ tr_status tr_autotune(tr_ctx *c, double *best_ms)
             }
         }
     if (bw > 0)
-        for (int im : {1, 2, 3, 4, 5}) {
+        for (int im : {1, 2, 3, 4, 5, 6, 7, 8}) {
+            if (im >= 6 && c->p.precision != TR_FP32C) break;
             double ms;
             if (timed(bw, bb, im, ms) && ms < best) {
                 best = ms;
@@ -2845,7 +3199,7 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
 {
     if (!c || !out) return TR_EINVAL;
     std::memset(out, 0, sizeof(*out));
-    unsigned long long st[4] = {0, 0, 0, 0};
+    unsigned long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t q[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(st, c->stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(q, c->queue, sizeof(q), hipMemcpyDeviceToHost, c->stream));
@@ -2862,6 +3216,10 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
     out->buffer_in_lds = c->last_lds;
     out->integration_wave = c->last_intw;
     out->lds_cas = c->last_cas;
+    out->integration_fp32 = c->last_int32;
+    out->rays_fp32 = (int64_t)st[3];
+    out->rays_fp64_again = (int64_t)st[4];
+    out->nodes_tabulated = (int64_t)st[5];
     out->overflow = q[1];
     float ms = 0;
     if (c->timed_valid && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) out->last_sweep_ms = ms;

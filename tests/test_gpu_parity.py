@@ -426,14 +426,16 @@ def test_launch_shapes(T, orc, prec):
     f1, i1 = orc_sweep(orc, P, f_prev=f0)
     pr, tol = (T.TR_FP64, TOL64) if prec == "fp64" else (T.TR_FP32C, TOL32)
     front = None if prec == "fp64" else front_mask(P, f1)
-    shapes = [(w, b, im, 0) for w in (1, 4, 16) for b in (1, 2) for im in (1, 2, 3, 4, 5)]
+    shapes = [(w, b, im, 0) for w in (1, 4, 16) for b in (1, 2) for im in (1, 2, 3, 4, 5, 6, 7, 8)]
     shapes += [(w, 1, 0, am) for w in (8, 16) for am in (1, 2)]   # the accumulation forms
     for waves, buf, im, am in shapes:
         name = f"shape waves {waves} buffer {buf} integration {im} atomics {am}"
         g0, j0, st = gpu_sweep(T, P, pr, thin=True, launch=(waves, 0, buf, im, am))
         assert (st.waves_per_target, st.buffer_in_lds) == (waves, int(buf == 1))
         if im:
-            assert st.integration_wave == {1: 1, 2: 64, 3: 4, 4: 8, 5: 16}[im]
+            assert st.integration_wave == {1: 1, 2: 64, 3: 4, 4: 8, 5: 16, 6: 4, 7: 8, 8: 16}[im]
+            # the FP32 march exists for FP32 buffers; the FP64 form takes the FP64 groups
+            assert st.integration_fp32 == int(im >= 6 and prec == "fp32c")
         cas = prec == "fp32c" and buf == 1 and waves in (8, 16) and am != 1
         assert st.lds_cas == int(cas)
         compare(g0, j0, f0, i0, tol, name=name + " thin")
@@ -450,7 +452,7 @@ def test_split_ray_buffers(T, orc, waves):
     f0, i0 = orc_sweep(orc, P, thin=True)
     f1, i1 = orc_sweep(orc, P, f_prev=f0)
     front = front_mask(P, f1)
-    for im in (0, 1, 2):
+    for im in (0, 1, 2, 8):
         name = f"split waves {waves} integration {im}"
         g0, j0, st = gpu_sweep(T, P, T.TR_FP32C, thin=True, launch=(waves, 0, 0, im, 0))
         assert st.buffer_in_lds == 2
@@ -460,6 +462,31 @@ def test_split_ray_buffers(T, orc, waves):
     g1, j1, st = gpu_sweep(T, P, T.TR_FP64, f_prev=f0, launch=(waves, 0, 0, 0, 0))
     assert st.buffer_in_lds == 0
     compare(g1, j1, f1, i1, TOL64, name=f"fp64 waves {waves} device buffers")
+
+
+@pytest.mark.parametrize("make", [lambda: W.small_lognormal(16, n_src=6, seed=31, nside=4, n_radial=48),
+                                  lambda: W.small_amr(2, seed=32, n_src=12),
+                                  lambda: W.small_uniform(24, q=2e48, n_radial=40)])
+def test_fp32_march_across_fronts(T, orc, make):
+    """The FP32 ray march (integration 6-8) on absorbing sweeps that hold
+    ionisation fronts: zero previous flux (zeta_d = 2) and the oracle's own
+    thin flux.  Away from the front the flux agrees with the FP64 oracle to
+    1e-4 and the flags agree; some rays must have gone back to FP64 (a source
+    below 1e-2 of its emitted Phi) and most must have stayed in FP32."""
+    P = make()
+    f0, _ = orc_sweep(orc, P, thin=True)
+    for fp in (None, f0):
+        f1, i1 = orc_sweep(orc, P, f_prev=fp)
+        front = front_mask(P, f1)
+        for im in (6, 7, 8):
+            g1, j1, st = gpu_sweep(T, P, T.TR_FP32C, f_prev=fp, launch=(0, 0, 0, im, 0))
+            assert st.integration_fp32 == 1
+            log(f"{P.name} prev {'zero' if fp is None else 'thin'} integration {im}: rays in FP32 {st.rays_fp32}, "
+                f"again in FP64 {st.rays_fp64_again}, front cells {int(front.sum())}")
+            assert st.rays_fp32 > 0 and st.rays_fp64_again < st.rays_fp32
+            compare(g1, j1, f1, i1, TOL32, front=front, name=f"fp32 march {im}")
+        if fp is None:
+            assert st.rays_fp64_again > 0
 
 
 def test_errors(T):
@@ -490,7 +517,7 @@ def test_errors(T):
     assert e.value.status == T.TR_EINVAL
     assert math.isnan(o[2].item()) and o[0].item() > 0
     # launch options out of range; buffers that cannot fit in LDS at this size
-    for bad_launch in ((3, 0, 0, 0, 0), (4, -1, 0, 0, 0), (4, 0, 3, 0, 0), (4, 0, 0, 6, 0), (4, 0, 0, 0, 3)):
+    for bad_launch in ((3, 0, 0, 0, 0), (4, -1, 0, 0, 0), (4, 0, 3, 0, 0), (4, 0, 0, 9, 0), (4, 0, 0, 0, 3)):
         with pytest.raises(T.TreeRayError) as e:
             ctx.set_launch(*bad_launch)
         assert e.value.status == T.TR_EINVAL

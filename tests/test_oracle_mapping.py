@@ -139,3 +139,22 @@ def test_angular_weights_tend_to_cone_volume_fractions(orc, lo, hi, nside):
     assert err[16] < 0.03
     assert err[4] < 0.12
     assert err[48] < err[4]
+
+
+def test_angular_weights_depend_on_the_offset_alone(orc):
+    """A node's sub-point directions are taken from its exact integer offset to
+    the target (plus the sub-box fraction), so its angular weights are the
+    same wherever the pair sits in the domain and at any power-of-two cell
+    size: the property that lets the sweep tabulate them by offset."""
+    rng = np.random.default_rng(17)
+    for nside in (2, 4):
+        for _ in range(200):
+            size = int(rng.choice([1, 2, 4]))
+            xt = rng.integers(-6, 6, 3) + 0.5
+            lo = rng.integers(-14, 14, 3)
+            hi = lo + size
+            w = orc.node_pixels(nside, 4, lo, hi, xt)
+            shift = rng.integers(-10 ** 6, 10 ** 6, 3)
+            assert orc.node_pixels(nside, 4, lo + shift, hi + shift, xt + shift) == w
+            k = int(rng.choice([2, 4, 8]))
+            assert orc.node_pixels(nside, 4, lo * k, hi * k, xt * k) == w
