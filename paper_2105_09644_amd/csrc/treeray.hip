@@ -523,7 +523,7 @@ __device__ inline double drcp(double x)
 // Returns F_{0,k} in internal flux units.
 template <typename Real>
 __device__ double integrate_ray(const RayRows<Real> &R, int k, const double *r, const double *inv2r, int nr, int top,
-                                int nside, int zeta_g)
+                                int nside, int zeta_g, bool clear_eps)
 {
     const double inv4pi = 1.0 / (4.0 * kPi);
     const double ns = (double)nside;
@@ -604,6 +604,10 @@ __device__ double integrate_ray(const RayRows<Real> &R, int k, const double *r, 
             f0 += phi_load(R, k, j) * drcp(rj * rj);
         }
     }
+    // emission rows kept in device memory are left zero for the next target
+    // (the march reused them for Phi)
+    if (clear_eps)
+        for (int i = 1; i <= top; ++i) R.eps(k, i) = (Real)0;
     return f0;
 }
 
@@ -622,7 +626,7 @@ __device__ inline double point_value(const double v[2], int i)
 // F_{0,k} (uniform) in internal flux units.
 template <typename Real, int NH>
 __device__ double integrate_ray_wave(const RayRows<Real> &R, int k, const double *r, const double *inv2r, int nr,
-                                     int top, int nside, int zeta_g)
+                                     int top, int nside, int zeta_g, bool clear_eps)
 {
     const int lane = lane_id();
     const double inv4pi = 1.0 / (4.0 * kPi);
@@ -692,8 +696,11 @@ __device__ double integrate_ray_wave(const RayRows<Real> &R, int k, const double
     }
     double s = 0.0;
 #pragma unroll
-    for (int h = 0; h < NH; ++h)
+    for (int h = 0; h < NH; ++h) {
         if (live[h]) s += ph[h] * drcp(rp[h] * rp[h]);
+        // emission rows kept in device memory are left zero for the next target
+        if (clear_eps && ep[h] > 0.0) R.eps(k, lane + 64 * h) = (Real)0;
+    }
     return wave_sum(s);
 }
 
@@ -708,7 +715,8 @@ __device__ double integrate_ray_wave(const RayRows<Real> &R, int k, const double
 // units on every lane of the group.  Call with every lane active.
 template <typename Real>
 __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int tp, bool has_ray, int tmax,
-                                       const double *r, const double *inv2r, int nr, int nside, int zeta_g, bool &ovf)
+                                       const double *r, const double *inv2r, int nr, int nside, int zeta_g, bool &ovf,
+                                       bool clear_eps)
 {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
@@ -789,6 +797,8 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
         a1 = ai;
         fb1 = fbi;
     }
+    // emission rows kept in device memory are left zero for the next target
+    if (clear_eps && act && j > 0) R.eps(k, j) = (Real)0;
     return group_sum(live ? ph * drcp(rj * rj) : 0.0, G);
 }
 
@@ -808,7 +818,8 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
 // lane of the group.  Call with every lane active.
 __device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, int tp, bool has_ray, int tmax,
                                          float rcoef, const double *inv2r, int nr, int nside, int zeta_g,
-                                         float front_ratio, bool &ovf, bool &near, float &f_hi, float &f_lo)
+                                         float front_ratio, bool &ovf, bool &near, float &f_hi, float &f_lo,
+                                         bool clear_eps)
 {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
@@ -914,6 +925,9 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, 
     f_hi = th;
     f_lo = tl;
     near = ((uint32_t)(__ballot(flag) >> g0) & gmask) != 0u;
+    // emission rows kept in device memory are left zero for the next target
+    // (a ray marched again in FP64 is cleared there)
+    if (clear_eps && act && j > 0 && !near) R.eps(k, j) = 0.0f;
 }
 
 template <typename T>
@@ -1550,8 +1564,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     if (64 * m < per_ray && lane + 64 * m < per_ray) dst[lane + 64 * m] = val[m];
             }
             for (int k = tid; k < npix; k += WAVES * 64) top[k] = 0;
-            if (split)
-                for (int e = tid; e < npix * nrm; e += WAVES * 64) eplane[e] = (Real)0;
+            // (the emission plane of split buffers is zero here: cleared when
+            // allocated and, entry by entry, by the march that reads it)
         }
         __syncthreads();
 
@@ -1592,6 +1606,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         }
         __syncthreads();
         if (scb[S_OVF]) {
+            // the partly mapped emission is not integrated: clear the plane
+            if (split)
+                for (int e = tid; e < npix * nrm; e += WAVES * 64) eplane[e] = (Real)0;
             if (tid == 0) {
                 bool queued = false;
                 if (!FALLBACK && a.ovf) {
@@ -1655,7 +1672,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                         bool near = false;
                         float fh = 0.0f, fl = 0.0f;
                         integrate_rays_group_f32(R, G, has ? myk : 0, mytp, has, tmax, rcoef, rd2, nr, a.nside,
-                                                 a.zeta_g, a.front_ratio, ovf, near, fh, fl);
+                                                 a.zeta_g, a.front_ratio, ovf, near, fh, fl, split);
                         const bool ok = head && has && !ovf;
                         if (ok && !near) {
                             float sh, se;
@@ -1669,7 +1686,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                         if (__ballot(head && redo)) {
                             bool ovf2 = false;
                             const double f = integrate_rays_group<Real>(R, G, redo ? myk : 0, mytp, redo, tmax, rd,
-                                                                        rd2, nr, a.nside, a.zeta_g, ovf2);
+                                                                        rd2, nr, a.nside, a.zeta_g, ovf2, split);
                             if (head && redo) fsum += f;
                             n_f64 += head && redo ? 1.0 : 0.0;
                         }
@@ -1677,7 +1694,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 }
                 if (!fp32_done) {
                     const double f = integrate_rays_group<Real>(R, G, has ? myk : 0, mytp, has, tmax, rd, rd2, nr,
-                                                                a.nside, a.zeta_g, ovf);
+                                                                a.nside, a.zeta_g, ovf, split);
                     if (head && has && !ovf) fsum += f;
                 }
                 // a ray with more emitting points than the group has lanes: a wave
@@ -1687,8 +1704,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     om &= om - 1;
                     const int k = __builtin_amdgcn_readlane(myk, l), tk = __builtin_amdgcn_readlane(mytp, l);
                     const double fw =
-                        nr > 64 ? integrate_ray_wave<Real, 2>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g)
-                                : integrate_ray_wave<Real, 1>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g);
+                        nr > 64 ? integrate_ray_wave<Real, 2>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g, split)
+                                : integrate_ray_wave<Real, 1>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g, split);
                     if (lane == 0) fsum += fw;
                 }
             }
@@ -1704,8 +1721,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     if (seen % IW == wave) {
                         const int tk = __builtin_amdgcn_readlane(t, l);
                         const double f =
-                            nr > 64 ? integrate_ray_wave<Real, 2>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g)
-                                    : integrate_ray_wave<Real, 1>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g);
+                            nr > 64 ? integrate_ray_wave<Real, 2>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g, split)
+                                    : integrate_ray_wave<Real, 1>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g, split);
                         if (lane == 0) fsum += f;
                     }
                     ++seen;
@@ -1715,7 +1732,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             // a lane per ray: ray k on lane k % 64 of wave (k / 64) % IW
             for (int k = wave * 64 + lane; k < npix; k += 64 * IW) {
                 const int t = top[k];
-                if (t > 0) fsum += integrate_ray<Real>(R, k, rd, rd2, nr, t, a.nside, a.zeta_g);
+                if (t > 0) fsum += integrate_ray<Real>(R, k, rd, rd2, nr, t, a.nside, a.zeta_g, split);
             }
         }
         // the next target: claimed and walked into the other bank by the last wave
@@ -2379,6 +2396,9 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
             c->ebuf_bytes = 0;
             if (dalloc(c, &c->ebuf, need)) return TR_ENOMEM;
             c->ebuf_bytes = need;
+            // the sweeps keep the plane zero between targets
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid1((int64_t)(need / 4))), dim3(256), 0, c->stream, (int32_t *)c->ebuf,
+                               (int64_t)(need / 4), 0);
         }
     }
     return TR_OK;
