@@ -213,7 +213,7 @@ def main():
                    steps=steps, warmup=warmup, accepted=int(acc), tested=int(tested), guard=int(guard),
                    waves=st.waves_per_target, per_cu=st.targets_per_cu, lds=st.buffer_in_lds,
                    nr=st.n_radial_max, intw=st.integration_wave, cas=st.lds_cas, int32=st.integration_fp32,
-                   rays32=st.rays_fp32, rays64=st.rays_fp64_again, tab=st.nodes_tabulated)
+                   rays32=st.rays_fp32, rays64=st.rays_fp64_again, tab=st.nodes_tabulated, regrouped=st.rays_regrouped)
         im = INT_MODE[res["intw"]] + (3 if res["int32"] else 0)
         res["launch"] = f"{res['waves']},{res['per_cu']},{1 if res['lds'] else 2},{im},{2 if res['cas'] else 1}"
         log(f"{name}: {res['ms_per_step']:.2f} ms/step, sweep {res['sweep_ms']:.2f} ms, launch {res['launch']}")
@@ -314,7 +314,7 @@ def main():
         "nodes_accepted_per_target": round(r["accepted"] / n_cells, 1),
         "nodes_tested_per_target": round(r["tested"] / n_cells, 1),
         "guard_recomputes_per_accepted_node": round(r["guard"] / max(1, r["accepted"]), 4),
-        "rays_marched_fp32": r["rays32"], "rays_marched_again_fp64": r["rays64"],
+        "rays_marched_fp32": r["rays32"], "rays_marched_again_fp64": r["rays64"], "rays_regrouped": r["regrouped"],
         "nodes_from_angular_table": round(r["tab"] / max(1, r["accepted"]), 4),
         "roofline": roof,
         "roofline_other": other,

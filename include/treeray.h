@@ -117,6 +117,8 @@ typedef struct {
                                    emitted Phi, or a close call between dying and surviving) */
     int64_t nodes_tabulated;    /* accepted nodes of the last sweep whose angular weights came from the
                                    context's table instead of their sub-points (same values) */
+    int64_t rays_regrouped;     /* rays of the last sweep with more emitting points than the launch's
+                                   group of lanes, marched by a wider group */
 } tr_stats;
 
 /* Creates a context on the current HIP device; stream may be NULL (default
@@ -189,7 +191,8 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec);
  * rays are integrated (0 = tuned or default, 1 = a lane per ray, 2 = a wave
  * per ray with the ray's points on the lanes, 3, 4, 5 = a group of 4, 8, 16
  * lanes per ray with the ray's emitting points on the lanes, the default; a
- * ray with more emitting points than that takes a wave; 6, 7, 8 = the same
+ * ray with more emitting points than that is marched again by a group of 32
+ * or 64 lanes (more than 64: a wave, in FP64); 6, 7, 8 = the same
  * groups marching in FP32 with a compensated Phi and compensated flux sums,
  * every ray where a source falls below 1e-2 of its emitted Phi marched again
  * in FP64 (Sec. 2.5; FP32C only, the FP64 form takes 3, 4, 5) and how the waves

@@ -50,7 +50,7 @@ class Stats(C.Structure):
                 ("buffer_in_lds", C.c_int32), ("overflow", C.c_int32), ("integration_wave", C.c_int32),
                 ("lds_cas", C.c_int32), ("integration_fp32", C.c_int32),
                 ("last_sweep_ms", C.c_double), ("rays_fp32", C.c_int64), ("rays_fp64_again", C.c_int64),
-                ("nodes_tabulated", C.c_int64)]
+                ("nodes_tabulated", C.c_int64), ("rays_regrouped", C.c_int64)]
 
 
 _lib = None

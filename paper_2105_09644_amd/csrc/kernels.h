@@ -68,16 +68,24 @@ __device__ inline double wave_sum(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over aligned groups of G lanes (G = 4, 8 or 16, uniform) with every
-// lane of a group ending with the same bits: lane swaps inside quads
+// Sum over aligned groups of G lanes (G = 4, 8, 16, 32 or 64, uniform) with
+// every lane of a group ending with the same bits: lane swaps inside quads
 // ([1,0,3,2], [2,3,0,1]), then the mirror inside 8 and inside 16 lanes; each
-// step adds two partial sums in either order, and addition commutes.  Call
-// with every lane active.
+// step adds two partial sums in either order, and addition commutes.  Groups
+// of 32 or 64 lanes then add the sums of their rows of 16, read from the
+// rows' first lanes into scalars.  Call with every lane active.
 template <int CTRL>
 __device__ inline double dpp_swap_d(double v)
 {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double read_lane_d(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
 }
 
@@ -87,6 +95,11 @@ __device__ inline double group_sum(double v, int G)
     v += dpp_swap_d<0x4E>(v);
     if (G >= 8) v += dpp_swap_d<0x141>(v);
     if (G >= 16) v += dpp_swap_d<0x140>(v);
+    if (G >= 32) {
+        const double h0 = read_lane_d(v, 0) + read_lane_d(v, 16);
+        const double h1 = read_lane_d(v, 32) + read_lane_d(v, 48);
+        v = G == 64 ? h0 + h1 : (lane_id() < 32 ? h0 : h1);
+    }
     return v;
 }
 
@@ -97,12 +110,22 @@ __device__ inline float dpp_swap_f(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
+__device__ inline float read_lane_f(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 __device__ inline float group_sum(float v, int G)
 {
     v += dpp_swap_f<0xB1>(v);
     v += dpp_swap_f<0x4E>(v);
     if (G >= 8) v += dpp_swap_f<0x141>(v);
     if (G >= 16) v += dpp_swap_f<0x140>(v);
+    if (G >= 32) {
+        const float h0 = read_lane_f(v, 0) + read_lane_f(v, 16);
+        const float h1 = read_lane_f(v, 32) + read_lane_f(v, 48);
+        v = G == 64 ? h0 + h1 : (lane_id() < 32 ? h0 : h1);
+    }
     return v;
 }
 
@@ -134,6 +157,61 @@ __device__ inline void group_csum(float &hi, float &lo, int G)
     csum_step<0x4E>(hi, lo);
     if (G >= 8) csum_step<0x141>(hi, lo);
     if (G >= 16) csum_step<0x140>(hi, lo);
+    if (G >= 32) {
+        // the rows' pairs, added pairwise with the same compensation
+        float h[2], l[2];
+        for (int q = 0; q < 2; ++q) {
+            float s, e;
+            two_sum(read_lane_f(hi, 32 * q), read_lane_f(hi, 32 * q + 16), s, e);
+            h[q] = s;
+            l[q] = (read_lane_f(lo, 32 * q) + read_lane_f(lo, 32 * q + 16)) + e;
+        }
+        if (G == 64) {
+            float s, e;
+            two_sum(h[0], h[1], s, e);
+            hi = s;
+            lo = (l[0] + l[1]) + e;
+        } else {
+            const bool first = lane_id() < 32;
+            hi = first ? h[0] : h[1];
+            lo = first ? l[0] : l[1];
+        }
+    }
+}
+
+// Position of the n-th (from 0) set bit of m; n < popcount(m).  A binary
+// search on the popcounts of the low halves.
+__device__ inline int nth_set_bit(uint64_t m, int n)
+{
+    uint32_t w = (uint32_t)m;
+    int pos = 0, c = __popc(w);
+    if (n >= c) {
+        n -= c;
+        w = (uint32_t)(m >> 32);
+        pos = 32;
+    }
+#pragma unroll
+    for (int b = 16; b >= 1; b >>= 1) {
+        c = __popc(w & ((1u << b) - 1u));
+        if (n >= c) {
+            n -= c;
+            w >>= b;
+            pos += b;
+        }
+    }
+    return pos;
+}
+
+// Largest value over the 64 lanes (values >= 0), the same on every lane.
+__device__ inline int wave_max_nonneg(int v)
+{
+    v = max(v, dpp_shr1(v));
+    v = max(v, dpp_shr2(v));
+    v = max(v, dpp_shr4(v));
+    v = max(v, dpp_shr8(v));
+    v = max(v, dpp_bc15(v));
+    v = max(v, dpp_bc31(v));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Exclusive prefix sum over the 64 lanes with DPP (no LDS): an inclusive

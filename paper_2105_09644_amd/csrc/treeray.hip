@@ -704,42 +704,51 @@ __device__ double integrate_ray_wave(const RayRows<Real> &R, int k, const double
     return wave_sum(s);
 }
 
-// The same march with a group of G lanes per ray (G = 4, 8 or 16), so that a
+// Slot s of a group of G lanes (G = 4 .. 64, uniform; sl = lane % G, g0 the
+// group's first lane) gets the s-th emitting point 1 .. tp of ray k in row
+// order (-1: none); cnt returns the ray's number of emitting points.
+template <typename Real>
+__device__ inline int group_emitter(const RayRows<Real> &R, int G, int sl, int g0, int k, int tp, bool has_ray,
+                                    int tmax, int &cnt)
+{
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    int j = -1;
+    cnt = 0;
+    for (int c0 = 1; c0 <= tmax; c0 += G) {
+        const int i = c0 + sl;
+        const bool em = has_ray && i <= tp && R.eps(k, i) > (Real)0;
+        const uint64_t gm = (__ballot(em) >> g0) & gmask;
+        const int rank = sl - cnt, n = __popcll(gm);
+        if (rank >= 0 && rank < n) j = c0 + nth_set_bit(gm, rank);
+        cnt += n;
+    }
+    return j;
+}
+
+// The same march with a group of G lanes per ray (G = 4 .. 64), so that a
 // wave integrates 64/G rays at once: slot s of the group holds the ray's s-th
 // emitting point j (in pixel-row order) with its Phi_j in a register, and
 // F_{i+1} is a group sum.  Every lane of a group reads the same point's
 // moments.  k / tp: this lane's ray (has_ray false: none) and its
 // outermost emitting point; tmax: the largest tp of the wave (uniform).  A
-// ray with more than G emitting points is left alone (ovf set on its lanes,
-// the caller integrates it another way).  Returns F_{0,k} in internal flux
-// units on every lane of the group.  Call with every lane active.
+// ray with more than G emitting points is left alone (n_over returns their
+// number on its lanes, else 0; the caller integrates it with more lanes).
+// Returns F_{0,k} in internal flux units on every lane of the group.  Call
+// with every lane active.
 template <typename Real>
 __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int tp, bool has_ray, int tmax,
-                                       const double *r, const double *inv2r, int nr, int nside, int zeta_g, bool &ovf,
-                                       bool clear_eps)
+                                       const double *r, const double *inv2r, int nr, int nside, int zeta_g,
+                                       int &n_over, bool clear_eps)
 {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
     const int g0 = lane - sl;   // first lane of the group
-    const uint32_t gmask = (uint32_t)((1ull << G) - 1ull);
     const double inv4pi = 1.0 / (4.0 * kPi);
     const double ns = (double)nside;
-    // emitting points 1 .. tp, G at a time; the group's n-th goes to slot n
-    int j = -1, cnt = 0;
-    for (int c0 = 1; c0 <= tmax; c0 += G) {
-        const int i = c0 + sl;
-        const bool em = has_ray && i <= tp && R.eps(k, i) > (Real)0;
-        const uint32_t gm = (uint32_t)(__ballot(em) >> g0) & gmask;
-        const int rank = sl - cnt;
-        if (rank >= 0 && rank < __popc(gm)) {
-            uint32_t x = gm;
-            for (int t = 0; t < rank; ++t) x &= x - 1u;
-            j = c0 + __ffs(x) - 1;
-        }
-        cnt += __popc(gm);
-    }
-    ovf = has_ray && cnt > G;
-    const bool act = has_ray && !ovf;
+    int cnt;
+    const int j = group_emitter(R, G, sl, g0, k, tp, has_ray, tmax, cnt);
+    n_over = has_ray && cnt > G ? cnt : 0;
+    const bool act = has_ray && cnt <= G;
     double rj = 0.0, i2rj = 0.0, epsj = 0.0;
     if (act && j > 0) {
         rj = r[j];
@@ -818,31 +827,20 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
 // lane of the group.  Call with every lane active.
 __device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, int tp, bool has_ray, int tmax,
                                          float rcoef, const double *inv2r, int nr, int nside, int zeta_g,
-                                         float front_ratio, bool &ovf, bool &near, float &f_hi, float &f_lo,
+                                         float front_ratio, int &n_over, bool &near, float &f_hi, float &f_lo,
                                          bool clear_eps)
 {
     const int lane = lane_id();
     const int sl = lane & (G - 1);
     const int g0 = lane - sl;
-    const uint32_t gmask = (uint32_t)((1ull << G) - 1ull);
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
     const float inv4pi = (float)(1.0 / (4.0 * kPi));
     const float ns = (float)nside;
     const float third = 1.0f / 3.0f;
-    int j = -1, cnt = 0;
-    for (int c0 = 1; c0 <= tmax; c0 += G) {
-        const int i = c0 + sl;
-        const bool em = has_ray && i <= tp && R.eps(k, i) > 0.0f;
-        const uint32_t gm = (uint32_t)(__ballot(em) >> g0) & gmask;
-        const int rank = sl - cnt;
-        if (rank >= 0 && rank < __popc(gm)) {
-            uint32_t x = gm;
-            for (int t = 0; t < rank; ++t) x &= x - 1u;
-            j = c0 + __ffs(x) - 1;
-        }
-        cnt += __popc(gm);
-    }
-    ovf = has_ray && cnt > G;
-    const bool act = has_ray && !ovf;
+    int cnt;
+    const int j = group_emitter(R, G, sl, g0, k, tp, has_ray, tmax, cnt);
+    n_over = has_ray && cnt > G ? cnt : 0;
+    const bool act = has_ray && cnt <= G;
     float i2rj = 0.0f, epsj = 0.0f, rj = 0.0f;
     const int j2 = j > 0 ? j * j : 0;
     if (act && j > 0) {
@@ -924,7 +922,7 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, 
     group_csum(th, tl, G);
     f_hi = th;
     f_lo = tl;
-    near = ((uint32_t)(__ballot(flag) >> g0) & gmask) != 0u;
+    near = ((__ballot(flag) >> g0) & gmask) != 0ull;
     // emission rows kept in device memory are left zero for the next target
     // (a ray marched again in FP64 is cleared there)
     if (clear_eps && act && j > 0 && !near) R.eps(k, j) = 0.0f;
@@ -1463,7 +1461,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     p += WAVES * sizeof(double);
     int *top = (int *)p;   // per ray: outermost point holding emission (0: none)
 
-    double n_acc = 0, n_test = 0, n_guard = 0, n_f32 = 0, n_f64 = 0, n_tab = 0;
+    double n_acc = 0, n_test = 0, n_guard = 0, n_f32 = 0, n_f64 = 0, n_tab = 0, n_re = 0;
     const int64_t n_items =
         FALLBACK ? min((int64_t)__hip_atomic_load(&a.queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ovf_cap)
                    : a.n_items;
@@ -1628,6 +1626,23 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         }
         n_acc += (wave == 0 && lane == 0) ? (double)scb[S_TOTAL] : 0.0;
 
+        // --- group integration: every emitting ray's number of emitting points
+        // sets the lanes it gets, a power of two from the launch's group up to
+        // 64 (more than 64 points: a wave); kept as bits 8.. of its top entry ---
+        if (a.int_group > 0) {
+            const int lg0 = 31 - __clz(a.int_group);
+            for (int k = wave; k < npix; k += WAVES) {
+                const int t = top[k];
+                if (t > 0) {
+                    int cnt = (int)__popcll(__ballot(lane + 1 <= t && R.eps(k, lane + 1) > (Real)0));
+                    if (t > 64) cnt += (int)__popcll(__ballot(lane + 65 <= t && R.eps(k, lane + 65) > (Real)0));
+                    const int cls = cnt > 64 ? 7 : max(lg0, 32 - __clz(max(cnt, 1) - 1));   // ceil(log2 cnt)
+                    if (lane == 0) top[k] = t | (cls << 8);
+                }
+            }
+            __syncthreads();
+        }
+
         // --- per-ray integration and the sum over rays (rays without emission give 0),
         // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
         constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
@@ -1636,44 +1651,71 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         if (wave >= IW) {
             // no rays here
         } else if (a.int_group > 0) {
-            // a group of G lanes per ray: the s-th emitting ray in pixel order goes
-            // to wave (s / NG) % IW, group s % NG, so the rays of a target fill
-            // few waves
-            const int G = a.int_group, NG = 64 / G;
-            int n_emit = 0;
-            for (int base = 0; base < npix; base += 64)
-                n_emit += (int)__popcll(__ballot(base + lane < npix && top[base + lane] > 0));
-            for (int r0 = wave * NG; r0 < n_emit; r0 += NG * IW) {
-                int myk = -1, mytp = 0, tmax = 0, seen = 0;
-                for (int base = 0; base < npix && seen < r0 + NG; base += 64) {
+            // rays of one class share a batch: 64 / g rays of g lanes each.  The
+            // batches, widest class first and pixel order within a class, are
+            // dealt round robin over the waves.
+            const int lg0 = 31 - __clz(a.int_group);
+            int nb[6];   // batches of classes 2 .. 7 (class 7: a ray each)
+            {
+                int n[6] = {0, 0, 0, 0, 0, 0};
+                for (int base = 0; base < npix; base += 64) {
                     const int t = base + lane < npix ? top[base + lane] : 0;
-                    uint64_t m = __ballot(t > 0);
-                    while (m && seen < r0 + NG) {
-                        const int l = __ffsll((unsigned long long)m) - 1;
-                        m &= m - 1;
-                        if (seen >= r0) {
-                            const int tk = __builtin_amdgcn_readlane(t, l);
-                            if (lane / G == seen - r0) {
-                                myk = base + l;
-                                mytp = tk;
-                            }
-                            tmax = max(tmax, tk);
-                        }
-                        ++seen;
-                    }
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) n[c] += (int)__popcll(__ballot(t > 0 && (t >> 8) == c + 2));
                 }
+                int re = 0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    nb[c] = c == 5 ? n[c] : (n[c] + (64 >> (c + 2)) - 1) >> (4 - c);
+                    if (c + 2 > lg0) re += n[c];
+                }
+                n_re += (wave == 0 && lane == 0) ? (double)re : 0.0;
+            }
+            const int n_batch = nb[0] + nb[1] + nb[2] + nb[3] + nb[4] + nb[5];
+            for (int b = wave; b < n_batch; b += IW) {
+                int cls = -1, bi = b;
+#pragma unroll
+                for (int c = 5; c >= 0; --c)
+                    if (cls < 0) {
+                        if (bi < nb[c]) cls = c + 2;
+                        else bi -= nb[c];
+                    }
+                const int ng = cls == 7 ? 1 : 64 >> cls;
+                // this lane's ray: the (bi ng + lane / g)-th of the class
+                const int want = bi * ng + (cls == 7 ? 0 : lane >> cls);
+                int myk = -1, mytp = 0, run = 0;
+                for (int base = 0; base < npix && run < bi * ng + ng; base += 64) {
+                    const int t = base + lane < npix ? top[base + lane] : 0;
+                    const uint64_t m = __ballot(t > 0 && (t >> 8) == cls);
+                    const int n = (int)__popcll(m), w = want - run;
+                    const bool mine = w >= 0 && w < n;
+                    const int pos = mine ? nth_set_bit(m, w) : 0;
+                    const int tv = __shfl(t, pos, 64);
+                    if (mine) {
+                        myk = base + pos;
+                        mytp = tv & 0xff;
+                    }
+                    run += n;
+                }
+                if (cls == 7) {
+                    const double fw = integrate_ray_wave<Real, 2>(R, myk, rd, rd2, nr, mytp, a.nside, a.zeta_g, split);
+                    if (lane == 0) fsum += fw;
+                    continue;
+                }
+                const int g = 1 << cls;
                 const bool has = myk >= 0;
-                bool ovf = false;
-                const bool head = (lane & (G - 1)) == 0;
+                const int tmax = wave_max_nonneg(mytp);
+                const bool head = (lane & (g - 1)) == 0;
+                int over = 0;   // zero: the class holds the ray's emitting points
                 bool fp32_done = false;
                 if constexpr (sizeof(Real) == 4) {
                     if (a.int_fp32) {
                         fp32_done = true;
                         bool near = false;
                         float fh = 0.0f, fl = 0.0f;
-                        integrate_rays_group_f32(R, G, has ? myk : 0, mytp, has, tmax, rcoef, rd2, nr, a.nside,
-                                                 a.zeta_g, a.front_ratio, ovf, near, fh, fl, split);
-                        const bool ok = head && has && !ovf;
+                        integrate_rays_group_f32(R, g, has ? myk : 0, mytp, has, tmax, rcoef, rd2, nr, a.nside,
+                                                 a.zeta_g, a.front_ratio, over, near, fh, fl, split);
+                        const bool ok = head && has;
                         if (ok && !near) {
                             float sh, se;
                             two_sum(cs_hi, fh, sh, se);
@@ -1682,31 +1724,19 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                         }
                         n_f32 += ok ? 1.0 : 0.0;
                         // the rays near an ionisation front, again in FP64
-                        const bool redo = has && !ovf && near;
+                        const bool redo = has && near;
                         if (__ballot(head && redo)) {
-                            bool ovf2 = false;
-                            const double f = integrate_rays_group<Real>(R, G, redo ? myk : 0, mytp, redo, tmax, rd,
-                                                                        rd2, nr, a.nside, a.zeta_g, ovf2, split);
+                            const double f = integrate_rays_group<Real>(R, g, redo ? myk : 0, mytp, redo, tmax, rd,
+                                                                        rd2, nr, a.nside, a.zeta_g, over, split);
                             if (head && redo) fsum += f;
                             n_f64 += head && redo ? 1.0 : 0.0;
                         }
                     }
                 }
                 if (!fp32_done) {
-                    const double f = integrate_rays_group<Real>(R, G, has ? myk : 0, mytp, has, tmax, rd, rd2, nr,
-                                                                a.nside, a.zeta_g, ovf, split);
-                    if (head && has && !ovf) fsum += f;
-                }
-                // a ray with more emitting points than the group has lanes: a wave
-                uint64_t om = __ballot(head && ovf);
-                while (om) {
-                    const int l = __ffsll((unsigned long long)om) - 1;
-                    om &= om - 1;
-                    const int k = __builtin_amdgcn_readlane(myk, l), tk = __builtin_amdgcn_readlane(mytp, l);
-                    const double fw =
-                        nr > 64 ? integrate_ray_wave<Real, 2>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g, split)
-                                : integrate_ray_wave<Real, 1>(R, k, rd, rd2, nr, tk, a.nside, a.zeta_g, split);
-                    if (lane == 0) fsum += fw;
+                    const double f = integrate_rays_group<Real>(R, g, has ? myk : 0, mytp, has, tmax, rd, rd2, nr,
+                                                                a.nside, a.zeta_g, over, split);
+                    if (head && has) fsum += f;
                 }
             }
         } else if (a.int_wave) {
@@ -1777,6 +1807,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     n_f32 = wave_sum(n_f32);
     n_f64 = wave_sum(n_f64);
     n_tab = wave_sum(n_tab);
+    n_re = wave_sum(n_re);
     if (lane == 0) {
         if (wave == 0 && n_acc > 0) atomicAdd(&a.stats[0], (unsigned long long)n_acc);
         if (n_test > 0) atomicAdd(&a.stats[1], (unsigned long long)n_test);
@@ -1784,6 +1815,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         if (n_f32 > 0) atomicAdd(&a.stats[3], (unsigned long long)n_f32);
         if (n_f64 > 0) atomicAdd(&a.stats[4], (unsigned long long)n_f64);
         if (n_tab > 0) atomicAdd(&a.stats[5], (unsigned long long)n_tab);
+        if (n_re > 0) atomicAdd(&a.stats[6], (unsigned long long)n_re);
     }
 }
 
@@ -3240,6 +3272,7 @@ tr_status tr_get_stats(tr_ctx *c, tr_stats *out)
     out->rays_fp32 = (int64_t)st[3];
     out->rays_fp64_again = (int64_t)st[4];
     out->nodes_tabulated = (int64_t)st[5];
+    out->rays_regrouped = (int64_t)st[6];
     out->overflow = q[1];
     float ms = 0;
     if (c->timed_valid && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) out->last_sweep_ms = ms;

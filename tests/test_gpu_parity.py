@@ -419,8 +419,8 @@ def test_launch_shapes(T, orc, prec):
     # every integration form (a lane, a wave, a group of 4, 8 or 16 lanes per
     # ray), both buffer places, 1, 4 and 16 waves per target and both
     # accumulation forms give the oracle's flux; 60 sources on 12 rays put more
-    # emitting points on a ray than a group of 4 or 8 lanes holds, so the wave
-    # fall-back runs too
+    # emitting points on a ray than a group of 4 or 8 lanes holds, so the
+    # wider groups run too
     P = W.small_lognormal(16, n_src=60, seed=7, nside=1, n_radial=24)
     f0, i0 = orc_sweep(orc, P, thin=True)
     f1, i1 = orc_sweep(orc, P, f_prev=f0)
@@ -441,6 +441,28 @@ def test_launch_shapes(T, orc, prec):
         compare(g0, j0, f0, i0, tol, name=name + " thin")
         g1, j1, _ = gpu_sweep(T, P, pr, f_prev=f0, launch=(waves, 0, buf, im, am))
         compare(g1, j1, f1, i1, tol, front=front, name=name + " absorbing")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_many_emitting_points(T, orc, prec):
+    # 4000 sources in 16^3 cells, 12 rays of 120 points, theta 0.3: rays hold
+    # from one to more than 64 emitting points, so the rays beyond a group of
+    # 4 or 16 lanes are marched again by groups of 8 to 64 lanes, and those
+    # beyond 64 points by a wave
+    P = W.small_lognormal(16, n_src=4000, seed=11, nside=1, n_radial=120, theta=0.3)
+    f0, i0 = orc_sweep(orc, P, thin=True)
+    f1, i1 = orc_sweep(orc, P, f_prev=f0)
+    pr, tol = (T.TR_FP64, TOL64) if prec == "fp64" else (T.TR_FP32C, TOL32)
+    front = None if prec == "fp64" else front_mask(P, f1)
+    for im in ((3, 5) if prec == "fp64" else (3, 6, 8)):
+        for waves in (4, 16):
+            name = f"{prec} many emitters waves {waves} integration {im}"
+            g0, j0, st = gpu_sweep(T, P, pr, thin=True, launch=(waves, 0, 0, im, 0))
+            log(f"{name}: rays regrouped {st.rays_regrouped}, in FP32 {st.rays_fp32}")
+            assert st.rays_regrouped > 0
+            compare(g0, j0, f0, i0, tol, name=name + " thin")
+            g1, j1, _ = gpu_sweep(T, P, pr, f_prev=f0, launch=(waves, 0, 0, im, 0))
+            compare(g1, j1, f1, i1, tol, front=front, name=name + " absorbing")
 
 
 @pytest.mark.parametrize("waves", [4, 16])
