@@ -707,9 +707,9 @@ __device__ double integrate_ray_wave(const RayRows<Real> &R, int k, const double
 // Slot s of a group of G lanes (G = 4 .. 64, uniform; sl = lane % G, g0 the
 // group's first lane) gets the s-th emitting point 1 .. tp of ray k in row
 // order (-1: none); cnt returns the ray's number of emitting points.
-template <typename Real>
-__device__ inline int group_emitter(const RayRows<Real> &R, int G, int sl, int g0, int k, int tp, bool has_ray,
-                                    int tmax, int &cnt)
+template <int G, typename Real>
+__device__ inline int group_emitter(const RayRows<Real> &R, int sl, int g0, int k, int tp, bool has_ray, int tmax,
+                                    int &cnt)
 {
     const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
     int j = -1;
@@ -735,8 +735,8 @@ __device__ inline int group_emitter(const RayRows<Real> &R, int G, int sl, int g
 // number on its lanes, else 0; the caller integrates it with more lanes).
 // Returns F_{0,k} in internal flux units on every lane of the group.  Call
 // with every lane active.
-template <typename Real>
-__device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int tp, bool has_ray, int tmax,
+template <typename Real, int G>
+__device__ double integrate_rays_group(const RayRows<Real> &R, int k, int tp, bool has_ray, int tmax,
                                        const double *r, const double *inv2r, int nr, int nside, int zeta_g,
                                        int &n_over, bool clear_eps)
 {
@@ -746,7 +746,7 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
     const double inv4pi = 1.0 / (4.0 * kPi);
     const double ns = (double)nside;
     int cnt;
-    const int j = group_emitter(R, G, sl, g0, k, tp, has_ray, tmax, cnt);
+    const int j = group_emitter<G>(R, sl, g0, k, tp, has_ray, tmax, cnt);
     n_over = has_ray && cnt > G ? cnt : 0;
     const bool act = has_ray && cnt <= G;
     double rj = 0.0, i2rj = 0.0, epsj = 0.0;
@@ -755,54 +755,42 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
         i2rj = inv2r[j];
         epsj = (double)R.eps(k, j);
     }
+    const double phjj = epsj * inv4pi;   // Phi_jj, emitted at r_j
     double ph = 0.0, a1 = 0.0, fb1 = 0.0;   // alpha and previous flux at r_{i+1}
     bool live = false;
-    // the point's moments are fetched one step ahead (zero beyond tp)
-    Real nV = 0, nA = 0, nE = 0;
-    if (act && tmax <= tp) {
-        nV = R.V(k, tmax);
-        nA = R.A(k, tmax);
-        nE = R.E(k, tmax);
-    }
+    // every step is predicated (selects, no branches on lane values); the
+    // moments are read one point ahead, beyond tp too (they meet no live source)
+    Real nV = R.V(k, tmax), nA = R.A(k, tmax), nE = R.E(k, tmax);
     for (int i = tmax; i >= 0; --i) {
         const double Vi = (double)nV, Ai = (double)nA, Ei = (double)nE;
-        if (act && i >= 1 && i - 1 <= tp) {
+        if (i >= 1) {
             nV = R.V(k, i - 1);
             nA = R.A(k, i - 1);
             nE = R.E(k, i - 1);
         }
-        double ai = 0.0, fbi = 0.0;
-        if (Vi > 0.0) {
-            const double rv = drcp(Vi);
-            ai = Ai * rv;
-            fbi = Ei * rv;
-        }
+        const double rv = drcp(Vi);
+        const double ai = Vi > 0.0 ? Ai * rv : 0.0;
+        const double fbi = Vi > 0.0 ? Ei * rv : 0.0;
         if (i <= nr - 2) {
             const double ri = r[i], ri1 = r[i + 1];
-            double f = 0.0;
-            if (live && j >= i + 2) {
-                const double B = rj - ri1;
-                f = ph * drcp(B * B);
-            }
+            const double A = rj - ri, B = rj - ri1;
+            const bool far = live && j >= i + 2;
+            const double fv = ph * drcp(B * B);
+            const double f = far ? fv : 0.0;
             const double ftot = group_sum(f, G);   // F_{i+1} of the group's ray
-            double g = 0.0;
-            if (ftot > 0.0) {
-                g = 2.0 * drcp(ftot);
-                if (fb1 > 0.0) g = fmin(g, drcp(fb1));
-            }
+            const double g2 = 2.0 * drcp(ftot);
+            const double gb = fmin(g2, drcp(fb1));
+            const double g = ftot > 0.0 ? (fb1 > 0.0 ? gb : g2) : 0.0;
             const double aseg = 0.5 * (ai + a1) * (ri1 - ri) * (1.0 / 3.0);
-            if (live) {
-                const double A = rj - ri, B = rj - ri1;
-                double z = j >= i + 2 ? f * g : 1.0;
-                if (zeta_g) z *= fmin(1.0, ns * A * i2rj);
-                ph = fmax(0.0, ph - aseg * (A * A + A * B + B * B) * z);
-                live = ph > 0.0;
-            }
+            double z = far ? f * g : 1.0;
+            if (zeta_g) z *= fmin(1.0, ns * A * i2rj);
+            const double nph = fmax(0.0, ph - aseg * (A * A + A * B + B * B) * z);
+            ph = live ? nph : ph;
+            live = live && nph > 0.0;
         }
-        if (act && i >= 1 && j == i) {
-            ph = epsj * inv4pi;
-            live = true;
-        }
+        const bool born = act && i >= 1 && j == i;
+        ph = born ? phjj : ph;
+        live = live || born;
         a1 = ai;
         fb1 = fbi;
     }
@@ -825,7 +813,8 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int G, int k, int
 // regime of an ionisation front -- near is set on the group and the caller
 // integrates that ray again in FP64.  Returns F_{0,k} as (hi, lo) on every
 // lane of the group.  Call with every lane active.
-__device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, int tp, bool has_ray, int tmax,
+template <int G>
+__device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, int tp, bool has_ray, int tmax,
                                          float rcoef, const double *inv2r, int nr, int nside, int zeta_g,
                                          float front_ratio, int &n_over, bool &near, float &f_hi, float &f_lo,
                                          bool clear_eps)
@@ -838,7 +827,7 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, 
     const float ns = (float)nside;
     const float third = 1.0f / 3.0f;
     int cnt;
-    const int j = group_emitter(R, G, sl, g0, k, tp, has_ray, tmax, cnt);
+    const int j = group_emitter<G>(R, sl, g0, k, tp, has_ray, tmax, cnt);
     n_over = has_ray && cnt > G ? cnt : 0;
     const bool act = has_ray && cnt <= G;
     float i2rj = 0.0f, epsj = 0.0f, rj = 0.0f;
@@ -848,68 +837,53 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, 
         epsj = R.eps(k, j);
         rj = rcoef * (float)j2;
     }
-    float ph = 0.0f, pl = 0.0f, ph0 = 0.0f, a1 = 0.0f, fb1 = 0.0f;
+    const float phjj = epsj * inv4pi;   // Phi_jj, emitted at r_j
+    float ph = 0.0f, pl = 0.0f, a1 = 0.0f, fb1 = 0.0f;
     bool live = false, flag = false;
-    float nV = 0.0f, nA = 0.0f, nE = 0.0f;
-    if (act && tmax <= tp) {
-        nV = R.V(k, tmax);
-        nA = R.A(k, tmax);
-        nE = R.E(k, tmax);
-    }
+    // every step is predicated (selects, no branches on lane values); the
+    // moments are read one point ahead, beyond tp too (they meet no live source)
+    float nV = R.V(k, tmax), nA = R.A(k, tmax), nE = R.E(k, tmax);
     for (int i = tmax; i >= 0; --i) {
         const float Vi = nV, Ai = nA, Ei = nE;
-        if (act && i >= 1 && i - 1 <= tp) {
+        if (i >= 1) {
             nV = R.V(k, i - 1);
             nA = R.A(k, i - 1);
             nE = R.E(k, i - 1);
         }
-        float ai = 0.0f, fbi = 0.0f;
-        if (Vi > 0.0f) {
-            const float rv = __builtin_amdgcn_rcpf(Vi);
-            ai = Ai * rv;
-            fbi = Ei * rv;
-        }
+        const float rv = __builtin_amdgcn_rcpf(Vi);
+        const float ai = Vi > 0.0f ? Ai * rv : 0.0f;
+        const float fbi = Vi > 0.0f ? Ei * rv : 0.0f;
         if (i <= nr - 2) {
             const int i1sq = (i + 1) * (i + 1);
-            float f = 0.0f, B = 0.0f;
-            if (live && j >= i + 2) {
-                B = rcoef * (float)(j2 - i1sq);
-                f = (ph + pl) * __builtin_amdgcn_rcpf(B * B);
-            }
+            const float A = rcoef * (float)(j2 - i * i), B = rcoef * (float)(j2 - i1sq);
+            const bool far = live && j >= i + 2;
+            const float fv = (ph + pl) * __builtin_amdgcn_rcpf(B * B);
+            const float f = far ? fv : 0.0f;
             const float ftot = group_sum(f, G);   // F_{i+1} of the group's ray
-            float g = 0.0f;
-            if (ftot > 0.0f) {
-                g = 2.0f * __builtin_amdgcn_rcpf(ftot);
-                if (fb1 > 0.0f) g = fminf(g, __builtin_amdgcn_rcpf(fb1));
-            }
+            const float g2 = 2.0f * __builtin_amdgcn_rcpf(ftot);
+            const float gb = fminf(g2, __builtin_amdgcn_rcpf(fb1));
+            const float g = ftot > 0.0f ? (fb1 > 0.0f ? gb : g2) : 0.0f;
             const float aseg = 0.5f * (ai + a1) * (rcoef * (float)(2 * i + 1)) * third;
-            if (live) {
-                const float A = rcoef * (float)(j2 - i * i);
-                if (j < i + 2) B = rcoef * (float)(j2 - i1sq);
-                float z = j >= i + 2 ? f * g : 1.0f;
-                if (zeta_g) z *= fminf(1.0f, ns * A * i2rj);
-                const float loss = aseg * (A * A + A * B + B * B) * z;
-                const float before = ph + pl;
-                float sh, se;
-                two_sum(ph, -loss, sh, se);
-                ph = sh;
-                pl += se;
-                const float after = ph + pl;
-                if (after > 0.0f) {
-                    flag |= after < front_ratio * ph0;
-                } else {
-                    flag |= loss < 1.001f * before;   // a close call: decide it in FP64
-                    ph = pl = 0.0f;
-                    live = false;
-                }
-            }
+            float z = far ? f * g : 1.0f;
+            if (zeta_g) z *= fminf(1.0f, ns * A * i2rj);
+            const float loss = aseg * (A * A + A * B + B * B) * z;
+            const float before = ph + pl;
+            float sh, se;
+            two_sum(ph, -loss, sh, se);
+            const float npl = pl + se;
+            const float after = sh + npl;
+            const bool alive = after > 0.0f;
+            // below front_ratio of Phi_jj, or a close call between dying and surviving
+            const bool risky = alive ? after < front_ratio * phjj : loss < 1.001f * before;
+            flag = flag || (live && risky);
+            ph = live ? (alive ? sh : 0.0f) : ph;
+            pl = live ? (alive ? npl : 0.0f) : pl;
+            live = live && alive;
         }
-        if (act && i >= 1 && j == i) {
-            ph = epsj * inv4pi;
-            pl = 0.0f;
-            ph0 = ph;
-            live = true;
-        }
+        const bool born = act && i >= 1 && j == i;
+        ph = born ? phjj : ph;
+        pl = born ? 0.0f : pl;
+        live = live || born;
         a1 = ai;
         fb1 = fbi;
     }
@@ -926,6 +900,51 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int G, int k, 
     // emission rows kept in device memory are left zero for the next target
     // (a ray marched again in FP64 is cleared there)
     if (clear_eps && act && j > 0 && !near) R.eps(k, j) = 0.0f;
+}
+
+// One batch of the group integration: 64 / G rays of G lanes each (myk < 0:
+// no ray on this group; mytp the ray's outermost emitting point).  Adds the
+// rays' F_{0,k} on their groups' first lanes: FP64 results into fsum, FP32
+// marched ones (FP32 buffers with the FP32 march) into the compensated pair
+// (cs_hi, cs_lo), a ray near an ionisation front marched again in FP64.
+template <typename Real, int G>
+__device__ __forceinline__ void march_batch(const SweepArgs &a, const RayRows<Real> &R, int myk, int mytp, Real rcoef,
+                                            const double *rd, const double *rd2, int nr, bool split, double &fsum,
+                                            float &cs_hi, float &cs_lo, double &n_f32, double &n_f64)
+{
+    const int lane = lane_id();
+    const bool has = myk >= 0;
+    const int tmax = wave_max_nonneg(mytp);
+    const bool head = (lane & (G - 1)) == 0;
+    int over = 0;   // zero: the ray's class holds its emitting points
+    if constexpr (sizeof(Real) == 4) {
+        if (a.int_fp32) {
+            bool near = false;
+            float fh = 0.0f, fl = 0.0f;
+            integrate_rays_group_f32<G>(R, has ? myk : 0, mytp, has, tmax, rcoef, rd2, nr, a.nside, a.zeta_g,
+                                        a.front_ratio, over, near, fh, fl, split);
+            const bool ok = head && has;
+            if (ok && !near) {
+                float sh, se;
+                two_sum(cs_hi, fh, sh, se);
+                cs_hi = sh;
+                cs_lo += se + fl;
+            }
+            n_f32 += ok ? 1.0 : 0.0;
+            // the rays near an ionisation front, again in FP64
+            const bool redo = has && near;
+            if (__ballot(head && redo)) {
+                const double f = integrate_rays_group<Real, G>(R, redo ? myk : 0, mytp, redo, tmax, rd, rd2, nr,
+                                                               a.nside, a.zeta_g, over, split);
+                if (head && redo) fsum += f;
+                n_f64 += head && redo ? 1.0 : 0.0;
+            }
+            return;
+        }
+    }
+    const double f = integrate_rays_group<Real, G>(R, has ? myk : 0, mytp, has, tmax, rd, rd2, nr, a.nside, a.zeta_g,
+                                                   over, split);
+    if (head && has) fsum += f;
 }
 
 template <typename T>
@@ -1702,41 +1721,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     if (lane == 0) fsum += fw;
                     continue;
                 }
-                const int g = 1 << cls;
-                const bool has = myk >= 0;
-                const int tmax = wave_max_nonneg(mytp);
-                const bool head = (lane & (g - 1)) == 0;
-                int over = 0;   // zero: the class holds the ray's emitting points
-                bool fp32_done = false;
-                if constexpr (sizeof(Real) == 4) {
-                    if (a.int_fp32) {
-                        fp32_done = true;
-                        bool near = false;
-                        float fh = 0.0f, fl = 0.0f;
-                        integrate_rays_group_f32(R, g, has ? myk : 0, mytp, has, tmax, rcoef, rd2, nr, a.nside,
-                                                 a.zeta_g, a.front_ratio, over, near, fh, fl, split);
-                        const bool ok = head && has;
-                        if (ok && !near) {
-                            float sh, se;
-                            two_sum(cs_hi, fh, sh, se);
-                            cs_hi = sh;
-                            cs_lo += se + fl;
-                        }
-                        n_f32 += ok ? 1.0 : 0.0;
-                        // the rays near an ionisation front, again in FP64
-                        const bool redo = has && near;
-                        if (__ballot(head && redo)) {
-                            const double f = integrate_rays_group<Real>(R, g, redo ? myk : 0, mytp, redo, tmax, rd,
-                                                                        rd2, nr, a.nside, a.zeta_g, over, split);
-                            if (head && redo) fsum += f;
-                            n_f64 += head && redo ? 1.0 : 0.0;
-                        }
-                    }
-                }
-                if (!fp32_done) {
-                    const double f = integrate_rays_group<Real>(R, g, has ? myk : 0, mytp, has, tmax, rd, rd2, nr,
-                                                                a.nside, a.zeta_g, over, split);
-                    if (head && has) fsum += f;
+                switch (cls) {
+                    case 2: march_batch<Real, 4>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    case 3: march_batch<Real, 8>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    case 4: march_batch<Real, 16>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    case 5: march_batch<Real, 32>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    default: march_batch<Real, 64>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
                 }
             }
         } else if (a.int_wave) {
