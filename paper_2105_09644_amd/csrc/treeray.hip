@@ -759,7 +759,10 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int k, int tp, bo
     double ph = 0.0, a1 = 0.0, fb1 = 0.0;   // alpha and previous flux at r_{i+1}
     bool live = false;
     // every step is predicated (selects, no branches on lane values); the
-    // moments are read one point ahead, beyond tp too (they meet no live source)
+    // moments are read one point ahead, beyond tp too (they meet no live
+    // source); r_{i+1} and B = r_j - r_{i+1} are the previous step's r_i and A
+    double ri1 = tmax + 1 < nr ? r[tmax + 1] : 0.0;
+    double Bv = rj - ri1, B2 = Bv * Bv;
     Real nV = R.V(k, tmax), nA = R.A(k, tmax), nE = R.E(k, tmax);
     for (int i = tmax; i >= 0; --i) {
         const double Vi = (double)nV, Ai = (double)nA, Ei = (double)nE;
@@ -771,28 +774,31 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int k, int tp, bo
         const double rv = drcp(Vi);
         const double ai = Vi > 0.0 ? Ai * rv : 0.0;
         const double fbi = Vi > 0.0 ? Ei * rv : 0.0;
+        const double ri = r[i];
+        const double A = rj - ri, A2 = A * A;
         if (i <= nr - 2) {
-            const double ri = r[i], ri1 = r[i + 1];
-            const double A = rj - ri, B = rj - ri1;
             const bool far = live && j >= i + 2;
-            const double fv = ph * drcp(B * B);
-            const double f = far ? fv : 0.0;
+            const double f = far ? ph * drcp(B2) : 0.0;
             const double ftot = group_sum(f, G);   // F_{i+1} of the group's ray
+            // min(2 / F_{i+1}, 1 / Fbar_{i+1}), used where f > 0 (so F_{i+1} > 0)
             const double g2 = 2.0 * drcp(ftot);
-            const double gb = fmin(g2, drcp(fb1));
-            const double g = ftot > 0.0 ? (fb1 > 0.0 ? gb : g2) : 0.0;
+            const double g = fb1 > 0.0 ? fmin(g2, drcp(fb1)) : g2;
             const double aseg = 0.5 * (ai + a1) * (ri1 - ri) * (1.0 / 3.0);
             double z = far ? f * g : 1.0;
             if (zeta_g) z *= fmin(1.0, ns * A * i2rj);
-            const double nph = fmax(0.0, ph - aseg * (A * A + A * B + B * B) * z);
-            ph = live ? nph : ph;
-            live = live && nph > 0.0;
+            const double nph = ph - aseg * (A2 + A * Bv + B2) * z;
+            const bool alive = live && nph > 0.0;
+            ph = alive ? nph : 0.0;
+            live = alive;
         }
         const bool born = act && i >= 1 && j == i;
         ph = born ? phjj : ph;
         live = live || born;
         a1 = ai;
         fb1 = fbi;
+        ri1 = ri;
+        Bv = A;
+        B2 = A2;
     }
     // emission rows kept in device memory are left zero for the next target
     if (clear_eps && act && j > 0) R.eps(k, j) = (Real)0;
@@ -839,9 +845,14 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, int tp,
     }
     const float phjj = epsj * inv4pi;   // Phi_jj, emitted at r_j
     float ph = 0.0f, pl = 0.0f, a1 = 0.0f, fb1 = 0.0f;
-    bool live = false, flag = false;
+    bool live = false, died = false;
+    float bd = 0.0f, ld = 0.0f;   // at the source's death: its Phi before the step and the step's loss
     // every step is predicated (selects, no branches on lane values); the
-    // moments are read one point ahead, beyond tp too (they meet no live source)
+    // moments are read one point ahead, beyond tp too (they meet no live
+    // source).  q = j^2 - i^2 exactly, so A = r_j - r_i = c q, and
+    // B = r_j - r_{i+1} is the previous step's A.
+    float q = (float)(j2 - (tmax + 1) * (tmax + 1));
+    float Bv = rcoef * q, B2 = Bv * Bv;
     float nV = R.V(k, tmax), nA = R.A(k, tmax), nE = R.E(k, tmax);
     for (int i = tmax; i >= 0; --i) {
         const float Vi = nV, Ai = nA, Ei = nE;
@@ -853,40 +864,46 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, int tp,
         const float rv = __builtin_amdgcn_rcpf(Vi);
         const float ai = Vi > 0.0f ? Ai * rv : 0.0f;
         const float fbi = Vi > 0.0f ? Ei * rv : 0.0f;
+        const float odd = (float)(2 * i + 1);
+        q += odd;
+        const float A = rcoef * q, A2 = A * A;
         if (i <= nr - 2) {
-            const int i1sq = (i + 1) * (i + 1);
-            const float A = rcoef * (float)(j2 - i * i), B = rcoef * (float)(j2 - i1sq);
             const bool far = live && j >= i + 2;
-            const float fv = (ph + pl) * __builtin_amdgcn_rcpf(B * B);
-            const float f = far ? fv : 0.0f;
+            const float f = far ? (ph + pl) * __builtin_amdgcn_rcpf(B2) : 0.0f;
             const float ftot = group_sum(f, G);   // F_{i+1} of the group's ray
-            const float g2 = 2.0f * __builtin_amdgcn_rcpf(ftot);
-            const float gb = fminf(g2, __builtin_amdgcn_rcpf(fb1));
-            const float g = ftot > 0.0f ? (fb1 > 0.0f ? gb : g2) : 0.0f;
-            const float aseg = 0.5f * (ai + a1) * (rcoef * (float)(2 * i + 1)) * third;
+            // min(2 / F_{i+1}, 1 / Fbar_{i+1}); used where f > 0 (so F_{i+1} > 0), and
+            // Fbar_{i+1} = 0 gives 1 / Fbar = +inf
+            const float g = fminf(2.0f * __builtin_amdgcn_rcpf(ftot), __builtin_amdgcn_rcpf(fb1));
+            const float aseg = 0.5f * (ai + a1) * (rcoef * odd) * third;
             float z = far ? f * g : 1.0f;
             if (zeta_g) z *= fminf(1.0f, ns * A * i2rj);
-            const float loss = aseg * (A * A + A * B + B * B) * z;
+            const float loss = aseg * (A2 + A * Bv + B2) * z;
             const float before = ph + pl;
             float sh, se;
             two_sum(ph, -loss, sh, se);
             const float npl = pl + se;
-            const float after = sh + npl;
-            const bool alive = after > 0.0f;
-            // below front_ratio of Phi_jj, or a close call between dying and surviving
-            const bool risky = alive ? after < front_ratio * phjj : loss < 1.001f * before;
-            flag = flag || (live && risky);
-            ph = live ? (alive ? sh : 0.0f) : ph;
-            pl = live ? (alive ? npl : 0.0f) : pl;
-            live = live && alive;
+            const bool alive = live && sh + npl > 0.0f;
+            const bool dies = live && !alive;
+            bd = dies ? before : bd;
+            ld = dies ? loss : ld;
+            died = died || dies;
+            ph = alive ? sh : 0.0f;
+            pl = alive ? npl : 0.0f;
+            live = alive;
         }
         const bool born = act && i >= 1 && j == i;
         ph = born ? phjj : ph;
-        pl = born ? 0.0f : pl;
         live = live || born;
         a1 = ai;
         fb1 = fbi;
+        Bv = A;
+        B2 = A2;
     }
+    // Phi only falls: a live source ended below front_ratio of Phi_jj, or a
+    // source died from below that or in a close call between dying and
+    // surviving (the step's loss within 1e-3 of what it had)
+    const float frp = front_ratio * phjj;
+    const bool flag = (live && ph + pl < frp) || (died && (bd < frp || ld < 1.001f * bd));
     float th = 0.0f, tl = 0.0f;
     if (live) {
         const float rr = __builtin_amdgcn_rcpf(rj * rj);
