@@ -466,13 +466,36 @@ __device__ inline int nearest_copy_shift(int v, int L)
 }
 
 // outermost emitting point of a ray
+// Per ray, a mask of the points 1 .. N_R - 1 that received emission: ew words
+// (1 for N_R <= 64, else 2) of 64 bits, bit i of word w for point 64 w + i.
 template <bool ATOMIC>
-__device__ inline void top_max(int *p, int v)
+__device__ inline void mask_or(unsigned long long *p, unsigned long long bits)
 {
     if constexpr (ATOMIC)
-        __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_or(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
-        *p = *p > v ? *p : v;
+        *p |= bits;
+}
+
+// marks points i0 (if e0) and i0 + 1 (if e1) of the ray whose mask starts at m
+template <bool ATOMIC>
+__device__ inline void mark_points(unsigned long long *m, int i0, bool e0, bool e1)
+{
+    const int i1 = i0 + 1;
+    const unsigned long long b0 = e0 && i0 >= 1 ? 1ull << (i0 & 63) : 0ull;
+    const unsigned long long b1 = e1 ? 1ull << (i1 & 63) : 0ull;
+    if ((i0 >> 6) == (i1 >> 6)) {
+        if (b0 | b1) mask_or<ATOMIC>(m + (i0 >> 6), b0 | b1);
+    } else {
+        if (b0) mask_or<ATOMIC>(m + (i0 >> 6), b0);
+        if (b1) mask_or<ATOMIC>(m + (i1 >> 6), b1);
+    }
+}
+
+// outermost marked point (0: none)
+__device__ inline int mask_top(unsigned long long w0, unsigned long long w1)
+{
+    return w1 ? 127 - __clzll((long long)w1) : (w0 ? 63 - __clzll((long long)w0) : 0);
 }
 
 // radial kernels by kind: 5 W_p, 6 W_g (App. A.1, A.2)
@@ -704,39 +727,32 @@ __device__ double integrate_ray_wave(const RayRows<Real> &R, int k, const double
     return wave_sum(s);
 }
 
-// Slot s of a group of G lanes (G = 4 .. 64, uniform; sl = lane % G, g0 the
-// group's first lane) gets the s-th emitting point 1 .. tp of ray k in row
-// order (-1: none); cnt returns the ray's number of emitting points.
-template <int G, typename Real>
-__device__ inline int group_emitter(const RayRows<Real> &R, int sl, int g0, int k, int tp, bool has_ray, int tmax,
-                                    int &cnt)
+// Slot sl of a group of G lanes gets the sl-th emitting point of its ray
+// (from the ray's mask (w0, w1) of points 1 .. N_R - 1; -1: none); cnt
+// returns the ray's number of emitting points.
+template <int G>
+__device__ inline int group_emitter(unsigned long long w0, unsigned long long w1, int sl, bool has_ray, int &cnt)
 {
-    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
-    int j = -1;
-    cnt = 0;
-    for (int c0 = 1; c0 <= tmax; c0 += G) {
-        const int i = c0 + sl;
-        const bool em = has_ray && i <= tp && R.eps(k, i) > (Real)0;
-        const uint64_t gm = (__ballot(em) >> g0) & gmask;
-        const int rank = sl - cnt, n = __popcll(gm);
-        if (rank >= 0 && rank < n) j = c0 + nth_set_bit(gm, rank);
-        cnt += n;
-    }
-    return j;
+    const int c0 = (int)__popcll(w0);
+    cnt = has_ray ? c0 + (int)__popcll(w1) : 0;
+    if (sl >= cnt) return -1;
+    return sl < c0 ? nth_set_bit(w0, sl) : 64 + nth_set_bit(w1, sl - c0);
 }
 
 // The same march with a group of G lanes per ray (G = 4 .. 64), so that a
 // wave integrates 64/G rays at once: slot s of the group holds the ray's s-th
 // emitting point j (in pixel-row order) with its Phi_j in a register, and
 // F_{i+1} is a group sum.  Every lane of a group reads the same point's
-// moments.  k / tp: this lane's ray (has_ray false: none) and its
-// outermost emitting point; tmax: the largest tp of the wave (uniform).  A
+// moments.  k / (w0, w1): this lane's ray (has_ray false: none) and its
+// mask of emitting points; tmax: the largest outermost emitting point of the
+// wave's rays (uniform).  A
 // ray with more than G emitting points is left alone (n_over returns their
 // number on its lanes, else 0; the caller integrates it with more lanes).
 // Returns F_{0,k} in internal flux units on every lane of the group.  Call
 // with every lane active.
 template <typename Real, int G>
-__device__ double integrate_rays_group(const RayRows<Real> &R, int k, int tp, bool has_ray, int tmax,
+__device__ double integrate_rays_group(const RayRows<Real> &R, int k, unsigned long long w0, unsigned long long w1,
+                                       bool has_ray, int tmax,
                                        const double *r, const double *inv2r, int nr, int nside, int zeta_g,
                                        int &n_over, bool clear_eps)
 {
@@ -746,7 +762,7 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int k, int tp, bo
     const double inv4pi = 1.0 / (4.0 * kPi);
     const double ns = (double)nside;
     int cnt;
-    const int j = group_emitter<G>(R, sl, g0, k, tp, has_ray, tmax, cnt);
+    const int j = group_emitter<G>(w0, w1, sl, has_ray, cnt);
     n_over = has_ray && cnt > G ? cnt : 0;
     const bool act = has_ray && cnt <= G;
     double rj = 0.0, i2rj = 0.0, epsj = 0.0;
@@ -759,8 +775,9 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int k, int tp, bo
     double ph = 0.0, a1 = 0.0, fb1 = 0.0;   // alpha and previous flux at r_{i+1}
     bool live = false;
     // every step is predicated (selects, no branches on lane values); the
-    // moments are read one point ahead, beyond tp too (they meet no live
-    // source); r_{i+1} and B = r_j - r_{i+1} are the previous step's r_i and A
+    // moments are read one point ahead, beyond the ray's outermost emitting
+    // point too (they meet no live source); r_{i+1} and B = r_j - r_{i+1} are
+    // the previous step's r_i and A
     double ri1 = tmax + 1 < nr ? r[tmax + 1] : 0.0;
     double Bv = rj - ri1, B2 = Bv * Bv;
     Real nV = R.V(k, tmax), nA = R.A(k, tmax), nE = R.E(k, tmax);
@@ -820,7 +837,8 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int k, int tp, bo
 // integrates that ray again in FP64.  Returns F_{0,k} as (hi, lo) on every
 // lane of the group.  Call with every lane active.
 template <int G>
-__device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, int tp, bool has_ray, int tmax,
+__device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, unsigned long long w0, unsigned long long w1,
+                                         bool has_ray, int tmax,
                                          float rcoef, const double *inv2r, int nr, int nside, int zeta_g,
                                          float front_ratio, int &n_over, bool &near, float &f_hi, float &f_lo,
                                          bool clear_eps)
@@ -833,7 +851,7 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, int tp,
     const float ns = (float)nside;
     const float third = 1.0f / 3.0f;
     int cnt;
-    const int j = group_emitter<G>(R, sl, g0, k, tp, has_ray, tmax, cnt);
+    const int j = group_emitter<G>(w0, w1, sl, has_ray, cnt);
     n_over = has_ray && cnt > G ? cnt : 0;
     const bool act = has_ray && cnt <= G;
     float i2rj = 0.0f, epsj = 0.0f, rj = 0.0f;
@@ -848,9 +866,9 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, int tp,
     bool live = false, died = false;
     float bd = 0.0f, ld = 0.0f;   // at the source's death: its Phi before the step and the step's loss
     // every step is predicated (selects, no branches on lane values); the
-    // moments are read one point ahead, beyond tp too (they meet no live
-    // source).  q = j^2 - i^2 exactly, so A = r_j - r_i = c q, and
-    // B = r_j - r_{i+1} is the previous step's A.
+    // moments are read one point ahead, beyond the ray's outermost emitting
+    // point too (they meet no live source).  q = j^2 - i^2 exactly, so
+    // A = r_j - r_i = c q, and B = r_j - r_{i+1} is the previous step's A.
     float q = (float)(j2 - (tmax + 1) * (tmax + 1));
     float Bv = rcoef * q, B2 = Bv * Bv;
     float nV = R.V(k, tmax), nA = R.A(k, tmax), nE = R.E(k, tmax);
@@ -920,25 +938,26 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, int tp,
 }
 
 // One batch of the group integration: 64 / G rays of G lanes each (myk < 0:
-// no ray on this group; mytp the ray's outermost emitting point).  Adds the
+// no ray on this group; (m0, m1) the ray's mask of emitting points).  Adds the
 // rays' F_{0,k} on their groups' first lanes: FP64 results into fsum, FP32
 // marched ones (FP32 buffers with the FP32 march) into the compensated pair
 // (cs_hi, cs_lo), a ray near an ionisation front marched again in FP64.
 template <typename Real, int G>
-__device__ __forceinline__ void march_batch(const SweepArgs &a, const RayRows<Real> &R, int myk, int mytp, Real rcoef,
+__device__ __forceinline__ void march_batch(const SweepArgs &a, const RayRows<Real> &R, int myk, unsigned long long m0,
+                                            unsigned long long m1, Real rcoef,
                                             const double *rd, const double *rd2, int nr, bool split, double &fsum,
                                             float &cs_hi, float &cs_lo, double &n_f32, double &n_f64)
 {
     const int lane = lane_id();
     const bool has = myk >= 0;
-    const int tmax = wave_max_nonneg(mytp);
+    const int tmax = wave_max_nonneg(mask_top(m0, m1));
     const bool head = (lane & (G - 1)) == 0;
     int over = 0;   // zero: the ray's class holds its emitting points
     if constexpr (sizeof(Real) == 4) {
         if (a.int_fp32) {
             bool near = false;
             float fh = 0.0f, fl = 0.0f;
-            integrate_rays_group_f32<G>(R, has ? myk : 0, mytp, has, tmax, rcoef, rd2, nr, a.nside, a.zeta_g,
+            integrate_rays_group_f32<G>(R, has ? myk : 0, m0, m1, has, tmax, rcoef, rd2, nr, a.nside, a.zeta_g,
                                         a.front_ratio, over, near, fh, fl, split);
             const bool ok = head && has;
             if (ok && !near) {
@@ -951,7 +970,7 @@ __device__ __forceinline__ void march_batch(const SweepArgs &a, const RayRows<Re
             // the rays near an ionisation front, again in FP64
             const bool redo = has && near;
             if (__ballot(head && redo)) {
-                const double f = integrate_rays_group<Real, G>(R, redo ? myk : 0, mytp, redo, tmax, rd, rd2, nr,
+                const double f = integrate_rays_group<Real, G>(R, redo ? myk : 0, m0, m1, redo, tmax, rd, rd2, nr,
                                                                a.nside, a.zeta_g, over, split);
                 if (head && redo) fsum += f;
                 n_f64 += head && redo ? 1.0 : 0.0;
@@ -959,7 +978,7 @@ __device__ __forceinline__ void march_batch(const SweepArgs &a, const RayRows<Re
             return;
         }
     }
-    const double f = integrate_rays_group<Real, G>(R, has ? myk : 0, mytp, has, tmax, rd, rd2, nr, a.nside, a.zeta_g,
+    const double f = integrate_rays_group<Real, G>(R, has ? myk : 0, m0, m1, has, tmax, rd, rd2, nr, a.nside, a.zeta_g,
                                                    over, split);
     if (head && has) fsum += f;
 }
@@ -1060,7 +1079,8 @@ __device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, 
 // in registers, so it makes no memory round trip besides its atomics.
 // KV: the radial-kernel variants of App. A (otherwise two-point W_f,3 and W_p)
 template <typename Real, int ATOMIC, bool KV>
-__device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, const int *per, const Real *rt, int nr,
+__device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned long long *emask, int ew, const int *per,
+                          const Real *rt, int nr,
                           Real rc_inv,
                           Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, int tsize, double &guard_count,
                           double &tab_count)
@@ -1277,7 +1297,6 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
         }
         const int jep = KV ? rdlane(epacked, j) : 0;
         const int jemode = jep & 3, jle = (jep >> 2) & 255, jne = (jep >> 10) & 255;
-        const int jetop = KV ? (jep >> 18) : (je1 != (Real)0 ? jie + 1 : jie);
         const bool has_eps = je0 != (Real)0 || je1 != (Real)0 || jemode != 0;
         const int span = jn < 64 ? jn : 64;                         // points per batch slot
         const int jdv = rdlane(divp, j);
@@ -1303,16 +1322,14 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
                                   rdlane(qeps, j);
         }
         const int slot_k = slot_kc & 0xffff, slot_c = slot_kc >> 16;
-        // emission: lane q deposits pixel q's share on the two bracket points
-        // (the spread forms go with A, E, V below); the ray's outermost emitting point
-        if (has_eps && lane < nd) {
-            if (jemode == 0) {
-                const Real wk = (Real)slot_c * inv_s3;
-                Real *row = &R.eps(slot_k, jie);
-                if (je0 != (Real)0) buf_add<Real, EATOMIC>(row, wk * je0);
-                if (je1 != (Real)0) buf_add<Real, EATOMIC>(row + 1, wk * je1);
-            }
-            top_max<ATOMIC != 0>(top + slot_k, jetop);
+        // emission: lane q deposits pixel q's share on the two bracket points and
+        // marks them in the ray's mask (the spread forms go with A, E, V below)
+        if (has_eps && lane < nd && jemode == 0) {
+            const Real wk = (Real)slot_c * inv_s3;
+            Real *row = &R.eps(slot_k, jie);
+            if (je0 != (Real)0) buf_add<Real, EATOMIC>(row, wk * je0);
+            if (je1 != (Real)0) buf_add<Real, EATOMIC>(row + 1, wk * je1);
+            mark_points<ATOMIC != 0>(emask + (size_t)slot_k * ew, jie, je0 != (Real)0, je1 != (Real)0);
         }
         // A, E, V: lanes cover (pixel slot, point) pairs, G slots at a time
         for (int b0 = 0; b0 < nd; b0 += G) {
@@ -1323,7 +1340,10 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
                 const Real wk = (Real)cq * inv_s3;
                 Real *row = &R.A(kq, jlo + io);
                 buf_add3<Real, ATOMIC>(row, wk * wa, row + nrm, wk * we, row + 2 * nrm, wk * wv);
-                if (KV && wq != (Real)0) buf_add<Real, EATOMIC>(&R.eps(kq, jlo + io), wk * wq);   // the emission row
+                if (KV && wq != (Real)0) {   // the emission row
+                    buf_add<Real, EATOMIC>(&R.eps(kq, jlo + io), wk * wq);
+                    mark_points<ATOMIC != 0>(emask + (size_t)kq * ew, jlo + io, true, false);
+                }
             }
         }
         if (jn > 64) {
@@ -1343,7 +1363,10 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, int *top, 
                         const Real q2 = emission_weight<Real>(jemode, i, i2, jle, jne, rdlane(ea, j), rdlane(eb, j), jfb,
                                                               rcoef, jd, jhinv, a.eps_kernel == K_G) *
                                         rdlane(qeps, j);
-                        if (q2 != (Real)0) buf_add<Real, EATOMIC>(&R.eps(k, jlo + i2), wk * q2);
+                        if (q2 != (Real)0) {
+                            buf_add<Real, EATOMIC>(&R.eps(k, jlo + i2), wk * q2);
+                            mark_points<ATOMIC != 0>(emask + (size_t)k * ew, jlo + i2, true, false);
+                        }
                     }
                 }
             }
@@ -1495,7 +1518,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     p += 2 * S_COUNT * sizeof(int);
     double *red = (double *)p;
     p += WAVES * sizeof(double);
-    int *top = (int *)p;   // per ray: outermost point holding emission (0: none)
+    // per ray: the mask of its points that hold emission (ew words)
+    const int ew = nrm > 64 ? 2 : 1;
+    unsigned long long *const emask = (unsigned long long *)p;
 
     double n_acc = 0, n_test = 0, n_guard = 0, n_f32 = 0, n_f64 = 0, n_tab = 0, n_re = 0;
     const int64_t n_items =
@@ -1597,7 +1622,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 for (int m = 0; m < 4 * kMaxRadial / 64; ++m)
                     if (64 * m < per_ray && lane + 64 * m < per_ray) dst[lane + 64 * m] = val[m];
             }
-            for (int k = tid; k < npix; k += WAVES * 64) top[k] = 0;
+            for (int e = tid; e < npix * ew; e += WAVES * 64) emask[e] = 0ull;
             // (the emission plane of split buffers is zero here: cleared when
             // allocated and, entry by entry, by the march that reads it)
         }
@@ -1635,7 +1660,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             }
             end = uniform(end);
             if (end <= start) break;
-            map_nodes<Real, ATOMIC, KV>(a, R, top, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
+            map_nodes<Real, ATOMIC, KV>(a, R, emask, ew, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
                                         tsize, n_guard, n_tab);
         }
         __syncthreads();
@@ -1662,23 +1687,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         }
         n_acc += (wave == 0 && lane == 0) ? (double)scb[S_TOTAL] : 0.0;
 
-        // --- group integration: every emitting ray's number of emitting points
-        // sets the lanes it gets, a power of two from the launch's group up to
-        // 64 (more than 64 points: a wave); kept as bits 8.. of its top entry ---
-        if (a.int_group > 0) {
-            const int lg0 = 31 - __clz(a.int_group);
-            for (int k = wave; k < npix; k += WAVES) {
-                const int t = top[k];
-                if (t > 0) {
-                    int cnt = (int)__popcll(__ballot(lane + 1 <= t && R.eps(k, lane + 1) > (Real)0));
-                    if (t > 64) cnt += (int)__popcll(__ballot(lane + 65 <= t && R.eps(k, lane + 65) > (Real)0));
-                    const int cls = cnt > 64 ? 7 : max(lg0, 32 - __clz(max(cnt, 1) - 1));   // ceil(log2 cnt)
-                    if (lane == 0) top[k] = t | (cls << 8);
-                }
-            }
-            __syncthreads();
-        }
-
         // --- per-ray integration and the sum over rays (rays without emission give 0),
         // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
         constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
@@ -1687,23 +1695,37 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         if (wave >= IW) {
             // no rays here
         } else if (a.int_group > 0) {
-            // rays of one class share a batch: 64 / g rays of g lanes each.  The
-            // batches, widest class first and pixel order within a class, are
-            // dealt round robin over the waves.
+            // Every emitting ray gets a group of lanes sized by its number of
+            // emitting points: a power of two from the launch's group up to 64
+            // (its class), more than 64 points a wave (class 7).  Rays of one
+            // class share a batch of 64 / g rays of g lanes; the batches, widest
+            // class first and pixel order within a class, are dealt round robin
+            // over the waves.
             const int lg0 = 31 - __clz(a.int_group);
+            auto ray_class = [&](int k, int &tp) -> int {   // 0: no emission
+                unsigned long long w0 = 0ull, w1 = 0ull;
+                if (k < npix) {
+                    w0 = emask[(size_t)k * ew];
+                    if (ew > 1) w1 = emask[(size_t)k * ew + 1];
+                }
+                tp = mask_top(w0, w1);
+                const int cnt = (int)(__popcll(w0) + __popcll(w1));
+                return cnt == 0 ? 0 : cnt > 64 ? 7 : max(lg0, 32 - __clz(cnt - 1));   // ceil(log2 cnt)
+            };
             int nb[6];   // batches of classes 2 .. 7 (class 7: a ray each)
             {
                 int n[6] = {0, 0, 0, 0, 0, 0};
                 for (int base = 0; base < npix; base += 64) {
-                    const int t = base + lane < npix ? top[base + lane] : 0;
+                    int tp;
+                    const int c = ray_class(base + lane, tp);
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) n[c] += (int)__popcll(__ballot(t > 0 && (t >> 8) == c + 2));
+                    for (int q = 0; q < 6; ++q) n[q] += (int)__popcll(__ballot(c == q + 2));
                 }
                 int re = 0;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    nb[c] = c == 5 ? n[c] : (n[c] + (64 >> (c + 2)) - 1) >> (4 - c);
-                    if (c + 2 > lg0) re += n[c];
+                for (int q = 0; q < 6; ++q) {
+                    nb[q] = q == 5 ? n[q] : (n[q] + (64 >> (q + 2)) - 1) >> (4 - q);
+                    if (q + 2 > lg0) re += n[q];
                 }
                 n_re += (wave == 0 && lane == 0) ? (double)re : 0.0;
             }
@@ -1711,25 +1733,26 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             for (int b = wave; b < n_batch; b += IW) {
                 int cls = -1, bi = b;
 #pragma unroll
-                for (int c = 5; c >= 0; --c)
+                for (int q = 5; q >= 0; --q)
                     if (cls < 0) {
-                        if (bi < nb[c]) cls = c + 2;
-                        else bi -= nb[c];
+                        if (bi < nb[q]) cls = q + 2;
+                        else bi -= nb[q];
                     }
                 const int ng = cls == 7 ? 1 : 64 >> cls;
                 // this lane's ray: the (bi ng + lane / g)-th of the class
                 const int want = bi * ng + (cls == 7 ? 0 : lane >> cls);
                 int myk = -1, mytp = 0, run = 0;
                 for (int base = 0; base < npix && run < bi * ng + ng; base += 64) {
-                    const int t = base + lane < npix ? top[base + lane] : 0;
-                    const uint64_t m = __ballot(t > 0 && (t >> 8) == cls);
+                    int tp;
+                    const int c = ray_class(base + lane, tp);
+                    const uint64_t m = __ballot(c == cls);
                     const int n = (int)__popcll(m), w = want - run;
                     const bool mine = w >= 0 && w < n;
                     const int pos = mine ? nth_set_bit(m, w) : 0;
-                    const int tv = __shfl(t, pos, 64);
+                    const int tv = __shfl(tp, pos, 64);
                     if (mine) {
                         myk = base + pos;
-                        mytp = tv & 0xff;
+                        mytp = tv;
                     }
                     run += n;
                 }
@@ -1738,19 +1761,27 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     if (lane == 0) fsum += fw;
                     continue;
                 }
+                // the ray's mask, for its group's lanes to find their emitting points
+                unsigned long long m0 = 0ull, m1 = 0ull;
+                if (myk >= 0) {
+                    m0 = emask[(size_t)myk * ew];
+                    if (ew > 1) m1 = emask[(size_t)myk * ew + 1];
+                }
                 switch (cls) {
-                    case 2: march_batch<Real, 4>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    case 3: march_batch<Real, 8>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    case 4: march_batch<Real, 16>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    case 5: march_batch<Real, 32>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    default: march_batch<Real, 64>(a, R, myk, mytp, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    case 2: march_batch<Real, 4>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    case 3: march_batch<Real, 8>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    case 4: march_batch<Real, 16>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    case 5: march_batch<Real, 32>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    default: march_batch<Real, 64>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
                 }
             }
         } else if (a.int_wave) {
             // a wave per ray, the emitting rays dealt round robin over the waves
             int seen = 0;
             for (int base = 0; base < npix; base += 64) {
-                const int t = base + lane < npix ? top[base + lane] : 0;
+                int t = 0;
+                if (base + lane < npix)
+                    t = mask_top(emask[(size_t)(base + lane) * ew], ew > 1 ? emask[(size_t)(base + lane) * ew + 1] : 0ull);
                 uint64_t m = __ballot(t > 0);
                 while (m) {
                     const int l = __ffsll((unsigned long long)m) - 1;
@@ -1768,7 +1799,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         } else {
             // a lane per ray: ray k on lane k % 64 of wave (k / 64) % IW
             for (int k = wave * 64 + lane; k < npix; k += 64 * IW) {
-                const int t = top[k];
+                const int t = mask_top(emask[(size_t)k * ew], ew > 1 ? emask[(size_t)k * ew + 1] : 0ull);
                 if (t > 0) fsum += integrate_ray<Real>(R, k, rd, rd2, nr, t, a.nside, a.zeta_g, split);
             }
         }
@@ -2271,7 +2302,7 @@ size_t sweep_lds_bytes(size_t real, int npix, int stride_k, int nrm, int fmax, i
     b += 2 * (size_t)fmax * 4 + (size_t)amax * 4;
     b += 2 * 16 * 4;
     b += (size_t)waves * 8;
-    b += (size_t)npix * 4;
+    b += (size_t)npix * 8 * (nrm > 64 ? 2 : 1);
     return b;
 }
 
