@@ -12,6 +12,7 @@ namespace tr {
 
 constexpr int kBlock = 8;          // cells per block edge
 constexpr int kMaxRadial = 128;    // evaluation points per ray (two 64-bit masks)
+constexpr int kAtabRatios = 4;    // angular-weight table: nodes of 1, 2, 4 and 8 target sizes
 constexpr int kMaxLevels = 24;
 constexpr int kGlobalList = 1 << 16;   // frontier / accepted-list entries of the fallback walk
 constexpr int kFallbackPerCu = 2;       // workgroups per compute unit in the fallback pass

@@ -368,14 +368,14 @@ struct SweepArgs {
     int64_t ovf_cap;
     int32_t *glist;
     int32_t gfmax, gamax;
-    // angular-weight table (NULL: none): for a node of 1, 2 or 4 times the
-    // target's size (ri = 0, 1, 2) at offset o in target sizes from the
+    // angular-weight table (NULL: none): for a node of 1, 2, 4 or 8 times the
+    // target's size (ri = 0 .. 3) at offset o in target sizes from the
     // target's lower corner, |o_a| <= atab_w[ri], the entry
     // atab_idx[atab_base[ri] + ((o_x + w)(2w + 1) + o_y + w)(2w + 1) + o_z + w]
     // = (first pair << 7) | pairs, each pair in atab_pool = pixel | count << 16
     const int32_t *atab_idx;
     const int32_t *atab_pool;
-    int32_t atab_w[3], atab_base[3];
+    int32_t atab_w[kAtabRatios], atab_base[kAtabRatios];
 };
 
 // ray buffer rows: eps, A (recombinations), E (previous flux x volume), V
@@ -1123,8 +1123,8 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
             bz += shz;
         }
         if (a.atab_idx && !(g.w & kPartialBit)) {
-            // a cube of 1, 2 or 4 target sizes: offsets of its corner in target sizes (exact)
-            const int ri = size == tsize ? 0 : (size == 2 * tsize ? 1 : (size == 4 * tsize ? 2 : -1));
+            // a cube of 1, 2, 4 or 8 target sizes: offsets of its corner in target sizes (exact)
+            const int ri = size == tsize ? 0 : size == 2 * tsize ? 1 : size == 4 * tsize ? 2 : size == 8 * tsize ? 3 : -1;
             if (ri >= 0) {
                 const int sh = __builtin_ctz((unsigned)tsize);
                 const int kx = (bx - ((tx - tsize) >> 1)) >> sh, ky = (by - ((ty - tsize) >> 1)) >> sh,
@@ -1235,6 +1235,12 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
     // per node (lane = node): sub-box origin relative to the target and sub-box steps, FP32
     const float ox = 0.5f * (float)(2 * bx - tx), oy = 0.5f * (float)(2 * by - ty), oz = 0.5f * (float)(2 * bz - tz);
     const float sx = (float)ex * inv_s, sy = (float)ey * inv_s, sz = (float)ez * inv_s;
+    // the table entries of the next node are fetched while one is mapped
+    auto fetch_kc = [&](int jj) -> int {
+        const int t = jj < cnt ? rdlane(tab, jj) : -1;
+        return t >= 0 && lane < (t & 127) ? a.atab_pool[(t >> 7) + lane] : 0;
+    };
+    int next_kc = fetch_kc(0);
     for (int j = 0; j < cnt; ++j) {
         // --- angular: slot q (lane q of slot_kc) holds the q-th distinct pixel
         // and its sub-point count (pixel < 2^16, count <= 64), packed so that one
@@ -1242,9 +1248,11 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
         // by classifying the node's sub-points ---
         int nd = 0, slot_kc = 0;
         const int jt = rdlane(tab, j);
+        const int this_kc = next_kc;
+        next_kc = fetch_kc(j + 1);
         if (jt >= 0) {
             nd = jt & 127;
-            if (lane < nd) slot_kc = a.atab_pool[(jt >> 7) + lane];
+            if (lane < nd) slot_kc = this_kc;
             tab_count += lane == 0 ? 1.0 : 0.0;
         } else {
             int pix = 0;
@@ -1912,12 +1920,13 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_cas_fallback(SweepArgs 
 // appearance over the sub-points.
 // ---------------------------------------------------------------------------
 struct AtabGeom {
-    int32_t w[3], base[3], nkeys;
+    int32_t w[kAtabRatios], base[kAtabRatios], nkeys;
 };
 
 __device__ inline void atab_key(const AtabGeom &G, int key, int &r, int &ox, int &oy, int &oz)
 {
-    int ri = key >= G.base[2] ? 2 : (key >= G.base[1] ? 1 : 0);
+    int ri = 0;
+    while (ri + 1 < kAtabRatios && key >= G.base[ri + 1]) ++ri;
     int k = key - G.base[ri];
     const int w = G.w[ri], n = 2 * w + 1;
     oz = k % n - w;
@@ -2535,7 +2544,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.gamax = kGlobalList;
     a.atab_idx = c->atab_idx;
     a.atab_pool = c->atab_pool;
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kAtabRatios; ++q) {
         a.atab_w[q] = c->atab.w[q];
         a.atab_base[q] = c->atab.base[q];
     }
@@ -2634,10 +2643,10 @@ tr_status build_angular_table(tr_ctx *c)
 {
     const int s = c->p.subsample, ns = c->p.nside;
     const double th = c->p.theta > 0.05 ? c->p.theta : 0.05;
-    const int cap[3] = {12, 20, 24};
+    const int cap[kAtabRatios] = {12, 20, 24, 40};
     AtabGeom G{};
     int64_t nk = 0;
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kAtabRatios; ++q) {
         const int w = std::min(cap[q], (int)std::ceil((2.0 / th + 1.0) * (double)(1 << q)));
         G.w[q] = w;
         G.base[q] = (int32_t)nk;
