@@ -102,11 +102,12 @@ typedef struct {
     int64_t n_cells, n_nodes;
     int64_t nodes_accepted;     /* summed over the targets of the last sweep */
     int64_t nodes_tested;
-    int64_t guard_recomputes;   /* FP32C: angular sub-points re-evaluated in FP64 */
+    int64_t guard_recomputes;   /* angular sub-points re-evaluated in FP64 (inside the FP32 guard band) */
     int32_t n_radial_max, depth_max;
     int32_t waves_per_target, targets_per_cu;   /* launch shape of the last sweep */
     int32_t buffer_in_lds;      /* where the last sweep kept its ray buffers: 1 LDS, 0 device memory,
-                                   2 (FP32) the A, E, V rows in LDS and the emission rows in device memory */
+                                   2 (FP32) the A, E, V rows in LDS and the emission rows in device memory,
+                                   3 LDS for part of the rays at a time (a target's rays in passes) */
     int32_t overflow;           /* nonzero if a walk list overflowed */
     int32_t integration_wave;   /* lanes that integrated one ray in the last sweep: 1, 4, 8, 16 or 64 */
     int32_t lds_cas;            /* 1 if the last sweep accumulated its LDS ray buffers by compare-and-swap */
@@ -187,7 +188,9 @@ tr_status tr_set_precision(tr_ctx *c, tr_precision prec);
 
 /* Launch shape of the sweep: waves per target (1,2,4,8,16), resident
  * targets per compute unit (0 = as many as fit), where a target's ray
- * buffer lives (0 = LDS when it fits, 1 = LDS, 2 = device memory) and how
+ * buffer lives (0 = LDS when it fits, else the split FP32 form, else LDS
+ * in passes over the rays, 1 = the same but an error when none fits,
+ * 2 = device memory) and how
  * rays are integrated (0 = tuned or default, 1 = a lane per ray, 2 = a wave
  * per ray with the ray's points on the lanes, 3, 4, 5 = a group of 4, 8, 16
  * lanes per ray with the ray's emitting points on the lanes, the default; a

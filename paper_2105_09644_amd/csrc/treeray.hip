@@ -368,6 +368,8 @@ struct SweepArgs {
     int64_t ovf_cap;
     int32_t *glist;
     int32_t gfmax, gamax;
+    int32_t pass_rays;   // > 0: the LDS ray buffers hold this many rays; a target's rays are mapped
+                         // and integrated in passes over consecutive pixel ranges
     // angular-weight table (NULL: none): for a node of 1, 2, 4 or 8 times the
     // target's size (ri = 0 .. 3) at offset o in target sizes from the
     // target's lower corner, |o_a| <= atab_w[ri], the entry
@@ -1082,8 +1084,8 @@ template <typename Real, int ATOMIC, bool KV>
 __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned long long *emask, int ew, const int *per,
                           const Real *rt, int nr,
                           Real rc_inv,
-                          Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, int tsize, double &guard_count,
-                          double &tab_count)
+                          Real rcoef, const int *acc, int cnt, int tx, int ty, int tz, int tsize, int k0, int np,
+                          double &guard_count, double &tab_count)
 {
     using R4 = typename R4T<Real>::T;
     // emission rows (few writes; in device memory when the A, E, V rows alone fill LDS): hardware atomics
@@ -1251,30 +1253,38 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
         const int this_kc = next_kc;
         next_kc = fetch_kc(j + 1);
         if (jt >= 0) {
-            nd = jt & 127;
-            if (lane < nd) slot_kc = this_kc;
-            tab_count += lane == 0 ? 1.0 : 0.0;
-        } else {
-            int pix = 0;
-            if constexpr (sizeof(Real) == 4) {
-                const float vx = fmaf(ca, rdlane(sx, j), rdlane(ox, j));
-                const float vy = fmaf(cb, rdlane(sy, j), rdlane(oy, j));
-                const float vz = fmaf(cc, rdlane(sz, j), rdlane(oz, j));
-                bool unsure = false;
-                pix = ang2pix_f(ns, vx, vy, vz, a.guard_tol, unsure);
-                unsure &= active;
-                if (__ballot(unsure)) {
-                    const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
-                    const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
-                    if (unsure) {
-                        pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
-                        guard_count += 1.0;
+            if (np == a.npix) {
+                nd = jt & 127;
+                if (lane < nd) slot_kc = this_kc;
+            } else {
+                // the pass's pixels only, as local ray indices
+                const int nall = jt & 127;
+                for (int q = 0; q < nall; ++q) {
+                    const int kc = __builtin_amdgcn_readlane(this_kc, q);
+                    const int kl = (kc & 0xffff) - k0;
+                    if ((unsigned)kl < (unsigned)np) {
+                        slot_kc = lane == nd ? (kl | (kc & ~0xffff)) : slot_kc;
+                        ++nd;
                     }
                 }
-            } else {
+            }
+            tab_count += lane == 0 ? 1.0 : 0.0;
+        } else {
+            // FP32 with a guard band, FP64 inside it: the FP64 classifier's pixel
+            // for every sub-point, in both precisions
+            const float vx = fmaf(ca, rdlane(sx, j), rdlane(ox, j));
+            const float vy = fmaf(cb, rdlane(sy, j), rdlane(oy, j));
+            const float vz = fmaf(cc, rdlane(sz, j), rdlane(oz, j));
+            bool unsure = false;
+            int pix = ang2pix_f(ns, vx, vy, vz, a.guard_tol, unsure);
+            unsure &= active;
+            if (__ballot(unsure)) {
                 const int jbx = rdlane(bx, j), jby = rdlane(by, j), jbz = rdlane(bz, j);
                 const int jex = rdlane(ex, j), jey = rdlane(ey, j), jez = rdlane(ez, j);
-                if (active) pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
+                if (unsure) {
+                    pix = subpoint_pix_d(ns, s, jbx, jby, jbz, jex, jey, jez, tx, ty, tz, ia, ib, ic);
+                    guard_count += 1.0;
+                }
             }
             if ((unsigned)pix >= (unsigned)a.npix) {
                 // cannot happen for a finite direction: reported, never written out of bounds
@@ -1288,9 +1298,12 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
                 const int k = __builtin_amdgcn_readlane(pix, first);
                 const uint64_t m = __ballot(pix == k) & rem;
                 rem &= ~m;
-                const int kc = k | ((int)__popcll(m) << 16);   // uniform
-                slot_kc = lane == nd ? kc : slot_kc;
-                ++nd;
+                // (a pass keeps its own pixels, as local ray indices)
+                if ((unsigned)(k - k0) < (unsigned)np) {
+                    const int kc = (k - k0) | ((int)__popcll(m) << 16);   // uniform
+                    slot_kc = lane == nd ? kc : slot_kc;
+                    ++nd;
+                }
             }
         }
         // --- radial weights: this lane serves support point lo + io of batch slot po ---
@@ -1396,8 +1409,14 @@ __device__ inline void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATO
 // during the previous target's integration
 enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_PRE, S_WALKED, S_COUNT = 16 };
 
+// Waits until this wave's device-memory stores have completed (vmcnt 0), so
+// that an LDS flag written next publishes them to the workgroup's other waves
+// (a workgroup-scope release does not wait for them).
+__device__ inline void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// dev_lists: acc is in device memory (the mappers read it after the LDS counts)
 __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx, int ty, int tz, int *fr0, int *fr1,
-                            int *acc, int *sc, int fmax, int amax, double &n_test)
+                            int *acc, int *sc, int fmax, int amax, double &n_test, bool dev_lists)
 {
     const int lane = lane_id();
     int *cur = fr0, *nxt = fr1;
@@ -1455,13 +1474,17 @@ __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx
             for (int c = 0; c < nch; ++c) nxt[nn + off + c] = fc + c;
             nacc += cacc;
             nn += tot;
-            if (cacc && lane == 0) lds_store(&sc[S_AVAIL], nacc);
+            if (cacc) {
+                if (dev_lists) wait_stores();
+                if (lane == 0) lds_store(&sc[S_AVAIL], nacc);
+            }
         }
         int *t = cur;
         cur = nxt;
         nxt = t;
         nfr = nn;
     }
+    if (dev_lists) wait_stores();
     if (lane == 0) {
         sc[S_TOTAL] = nacc;
         if (ovf) sc[S_OVF] = 1;
@@ -1482,7 +1505,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar loops over waves' work
     const int nrm = a.nr_max, npix = a.npix;
-    const size_t buf_elems = (size_t)npix * a.stride_k;
+    // rays held at once (all of them, or a.pass_rays per pass)
+    const int prays = a.pass_rays > 0 ? a.pass_rays : npix;
+    const int npass = (npix + prays - 1) / prays;
+    const size_t buf_elems = (size_t)prays * a.stride_k;
     char *p = smem;
     Real *buf;
     if constexpr (LDSBUF) {
@@ -1607,232 +1633,244 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             cached_dom = dom;
             cached_tsize = tsize;
         }
-        // ray buffer: zero emission, the target's own share of A, E, V
-        {
-            // every ray starts from the same 4 (split: 3) N_R values: lane l holds entries l + 64 m
-            const Real inv_npix = (Real)1 / (Real)npix;
-            const int per_ray = (split ? 3 : 4) * nrm;
-            Real val[4 * kMaxRadial / 64];
-#pragma unroll
-            for (int m = 0; m < 4 * kMaxRadial / 64; ++m) {
-                const int e = lane + 64 * m;
-                const int row = e / nrm + (split ? 1 : 0), i = e - (e / nrm) * nrm;
-                Real v = (Real)0;
-                if (e < per_ray && row != Q_EPS && i < nr) {
-                    const Real mom = row == Q_A ? tB.x : row == Q_E ? tB.y : tB.z;
-                    v = mom * (wself[i] * inv_npix);
-                }
-                val[m] = v;
-            }
-            for (int k = wave; k < npix; k += WAVES) {
-                Real *dst = buf + (size_t)k * a.stride_k;
-#pragma unroll
-                for (int m = 0; m < 4 * kMaxRadial / 64; ++m)
-                    if (64 * m < per_ray && lane + 64 * m < per_ray) dst[lane + 64 * m] = val[m];
-            }
-            for (int e = tid; e < npix * ew; e += WAVES * 64) emask[e] = 0ull;
-            // (the emission plane of split buffers is zero here: cleared when
-            // allocated and, entry by entry, by the march that reads it)
-        }
-        __syncthreads();
-
-        // --- wave 0 walks (unless the target was walked ahead); every wave maps ---
-        const int *per = a.periodic ? D.ext : nullptr;
-        if (wave == 0 && !scb[S_WALKED]) walk_target(a, D.root, per, tx, ty, tz, fr0, fr1, acc, scb, fmax, amax, n_test);
-        for (;;) {
-            // claims of CHUNK nodes; once the walk is done, smaller ones near the
-            // end of the list (a share of what is left), so the waves finish together
-            int start = 0, size = CHUNK;
-            if (lane == 0) {
-                if (lds_load(&scb[S_DONE])) {
-                    const int left = lds_load(&scb[S_TOTAL]) - lds_load(&scb[S_CLAIM]);
-                    size = min(CHUNK, max(4, left / (2 * WAVES)));
-                }
-                start = atomicAdd(&scb[S_CLAIM], size);
-            }
-            start = __shfl(start, 0, 64);
-            size = __shfl(size, 0, 64);
-            int end = 0;
-            for (;;) {
-                const int avail = lds_load(&scb[S_AVAIL]);
-                if (avail >= start + size) {
-                    end = start + size;
-                    break;
-                }
-                if (lds_load(&scb[S_DONE])) {
-                    const int total = lds_load(&scb[S_TOTAL]);
-                    end = min(start + size, total);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            end = uniform(end);
-            if (end <= start) break;
-            map_nodes<Real, ATOMIC, KV>(a, R, emask, ew, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
-                                        tsize, n_guard, n_tab);
-        }
-        __syncthreads();
-        if (scb[S_OVF]) {
-            // the partly mapped emission is not integrated: clear the plane
-            if (split)
-                for (int e = tid; e < npix * nrm; e += WAVES * 64) eplane[e] = (Real)0;
-            if (tid == 0) {
-                bool queued = false;
-                if (!FALLBACK && a.ovf) {
-                    const int q = atomicAdd(&a.queue[3], 1);
-                    if (q < a.ovf_cap) {
-                        a.ovf[q] = (int32_t)item;
-                        queued = true;
-                    }
-                }
-                if (!queued) {
-                    a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
-                    if (a.ion_out) a.ion_out[o] = 0;
-                    atomicOr(&a.queue[1], 1);
-                }
-            }
-            continue;
-        }
-        n_acc += (wave == 0 && lane == 0) ? (double)scb[S_TOTAL] : 0.0;
-
-        // --- per-ray integration and the sum over rays (rays without emission give 0),
-        // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
-        constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
         double fsum = 0.0;
         float cs_hi = 0.0f, cs_lo = 0.0f;   // compensated FP32 sum of this lane's FP32-marched rays
-        if (wave >= IW) {
-            // no rays here
-        } else if (a.int_group > 0) {
-            // Every emitting ray gets a group of lanes sized by its number of
-            // emitting points: a power of two from the launch's group up to 64
-            // (its class), more than 64 points a wave (class 7).  Rays of one
-            // class share a batch of 64 / g rays of g lanes; the batches, widest
-            // class first and pixel order within a class, are dealt round robin
-            // over the waves.
-            const int lg0 = 31 - __clz(a.int_group);
-            auto ray_class = [&](int k, int &tp) -> int {   // 0: no emission
-                unsigned long long w0 = 0ull, w1 = 0ull;
-                if (k < npix) {
-                    w0 = emask[(size_t)k * ew];
-                    if (ew > 1) w1 = emask[(size_t)k * ew + 1];
-                }
-                tp = mask_top(w0, w1);
-                const int cnt = (int)(__popcll(w0) + __popcll(w1));
-                return cnt == 0 ? 0 : cnt > 64 ? 7 : max(lg0, 32 - __clz(cnt - 1));   // ceil(log2 cnt)
-            };
-            int nb[6];   // batches of classes 2 .. 7 (class 7: a ray each)
+        bool overflowed = false;
+        // the rays in passes of prays consecutive pixels (one pass when all fit)
+        for (int pass = 0; pass < npass; ++pass) {
+            const int k0 = pass * prays, np = min(prays, npix - k0);
+            // ray buffer: zero emission, the target's own share of A, E, V
             {
-                int n[6] = {0, 0, 0, 0, 0, 0};
-                for (int base = 0; base < npix; base += 64) {
-                    int tp;
-                    const int c = ray_class(base + lane, tp);
+                // every ray starts from the same 4 (split: 3) N_R values: lane l holds entries l + 64 m
+                const Real inv_npix = (Real)1 / (Real)npix;
+                const int per_ray = (split ? 3 : 4) * nrm;
+                Real val[4 * kMaxRadial / 64];
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) n[q] += (int)__popcll(__ballot(c == q + 2));
+                for (int m = 0; m < 4 * kMaxRadial / 64; ++m) {
+                    const int e = lane + 64 * m;
+                    const int row = e / nrm + (split ? 1 : 0), i = e - (e / nrm) * nrm;
+                    Real v = (Real)0;
+                    if (e < per_ray && row != Q_EPS && i < nr) {
+                        const Real mom = row == Q_A ? tB.x : row == Q_E ? tB.y : tB.z;
+                        v = mom * (wself[i] * inv_npix);
+                    }
+                    val[m] = v;
                 }
-                int re = 0;
+                for (int k = wave; k < np; k += WAVES) {
+                    Real *dst = buf + (size_t)k * a.stride_k;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    nb[q] = q == 5 ? n[q] : (n[q] + (64 >> (q + 2)) - 1) >> (4 - q);
-                    if (q + 2 > lg0) re += n[q];
+                    for (int m = 0; m < 4 * kMaxRadial / 64; ++m)
+                        if (64 * m < per_ray && lane + 64 * m < per_ray) dst[lane + 64 * m] = val[m];
                 }
-                n_re += (wave == 0 && lane == 0) ? (double)re : 0.0;
+                for (int e = tid; e < np * ew; e += WAVES * 64) emask[e] = 0ull;
+                // a later pass maps the same accepted nodes again
+                if (pass > 0 && tid == 0) scb[S_CLAIM] = 0;
+                // (the emission plane of split buffers is zero here: cleared when
+                // allocated and, entry by entry, by the march that reads it)
             }
-            const int n_batch = nb[0] + nb[1] + nb[2] + nb[3] + nb[4] + nb[5];
-            for (int b = wave; b < n_batch; b += IW) {
-                int cls = -1, bi = b;
+            __syncthreads();
+
+            // --- wave 0 walks (unless the target was walked ahead); every wave maps ---
+            const int *per = a.periodic ? D.ext : nullptr;
+            if (pass == 0 && wave == 0 && !scb[S_WALKED])
+                walk_target(a, D.root, per, tx, ty, tz, fr0, fr1, acc, scb, fmax, amax, n_test, FALLBACK);
+            for (;;) {
+                // claims of CHUNK nodes; once the walk is done, smaller ones near the
+                // end of the list (a share of what is left), so the waves finish together
+                int start = 0, size = CHUNK;
+                if (lane == 0) {
+                    if (lds_load(&scb[S_DONE])) {
+                        const int left = lds_load(&scb[S_TOTAL]) - lds_load(&scb[S_CLAIM]);
+                        size = min(CHUNK, max(4, left / (2 * WAVES)));
+                    }
+                    start = atomicAdd(&scb[S_CLAIM], size);
+                }
+                start = __shfl(start, 0, 64);
+                size = __shfl(size, 0, 64);
+                int end = 0;
+                for (;;) {
+                    const int avail = lds_load(&scb[S_AVAIL]);
+                    if (avail >= start + size) {
+                        end = start + size;
+                        break;
+                    }
+                    if (lds_load(&scb[S_DONE])) {
+                        const int total = lds_load(&scb[S_TOTAL]);
+                        end = min(start + size, total);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                end = uniform(end);
+                if (end <= start) break;
+                map_nodes<Real, ATOMIC, KV>(a, R, emask, ew, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
+                                            tsize, k0, np, n_guard, n_tab);
+            }
+            __syncthreads();
+            if (scb[S_OVF]) {
+                // the partly mapped emission is not integrated: clear the plane
+                if (split)
+                    for (int e = tid; e < npix * nrm; e += WAVES * 64) eplane[e] = (Real)0;
+                if (tid == 0) {
+                    bool queued = false;
+                    if (!FALLBACK && a.ovf) {
+                        const int q = atomicAdd(&a.queue[3], 1);
+                        if (q < a.ovf_cap) {
+                            a.ovf[q] = (int32_t)item;
+                            queued = true;
+                        }
+                    }
+                    if (!queued) {
+                        a.f_out[o] = __longlong_as_double(0x7ff8000000000000ll);
+                        if (a.ion_out) a.ion_out[o] = 0;
+                        atomicOr(&a.queue[1], 1);
+                    }
+                }
+                overflowed = true;
+                break;
+            }
+            if (pass == 0) n_acc += (wave == 0 && lane == 0) ? (double)scb[S_TOTAL] : 0.0;
+
+            // --- per-ray integration and the sum over rays (rays without emission give 0),
+            // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
+            constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
+            if (wave >= IW) {
+                // no rays here
+            } else if (a.int_group > 0) {
+                // Every emitting ray gets a group of lanes sized by its number of
+                // emitting points: a power of two from the launch's group up to 64
+                // (its class), more than 64 points a wave (class 7).  Rays of one
+                // class share a batch of 64 / g rays of g lanes; the batches, widest
+                // class first and pixel order within a class, are dealt round robin
+                // over the waves.
+                const int lg0 = 31 - __clz(a.int_group);
+                auto ray_class = [&](int k, int &tp) -> int {   // 0: no emission
+                    unsigned long long w0 = 0ull, w1 = 0ull;
+                    if (k < np) {
+                        w0 = emask[(size_t)k * ew];
+                        if (ew > 1) w1 = emask[(size_t)k * ew + 1];
+                    }
+                    tp = mask_top(w0, w1);
+                    const int cnt = (int)(__popcll(w0) + __popcll(w1));
+                    return cnt == 0 ? 0 : cnt > 64 ? 7 : max(lg0, 32 - __clz(cnt - 1));   // ceil(log2 cnt)
+                };
+                int nb[6];   // batches of classes 2 .. 7 (class 7: a ray each)
+                {
+                    int n[6] = {0, 0, 0, 0, 0, 0};
+                    for (int base = 0; base < np; base += 64) {
+                        int tp;
+                        const int c = ray_class(base + lane, tp);
 #pragma unroll
-                for (int q = 5; q >= 0; --q)
-                    if (cls < 0) {
-                        if (bi < nb[q]) cls = q + 2;
-                        else bi -= nb[q];
+                        for (int q = 0; q < 6; ++q) n[q] += (int)__popcll(__ballot(c == q + 2));
                     }
-                const int ng = cls == 7 ? 1 : 64 >> cls;
-                // this lane's ray: the (bi ng + lane / g)-th of the class
-                const int want = bi * ng + (cls == 7 ? 0 : lane >> cls);
-                int myk = -1, mytp = 0, run = 0;
-                for (int base = 0; base < npix && run < bi * ng + ng; base += 64) {
-                    int tp;
-                    const int c = ray_class(base + lane, tp);
-                    const uint64_t m = __ballot(c == cls);
-                    const int n = (int)__popcll(m), w = want - run;
-                    const bool mine = w >= 0 && w < n;
-                    const int pos = mine ? nth_set_bit(m, w) : 0;
-                    const int tv = __shfl(tp, pos, 64);
-                    if (mine) {
-                        myk = base + pos;
-                        mytp = tv;
+                    int re = 0;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        nb[q] = q == 5 ? n[q] : (n[q] + (64 >> (q + 2)) - 1) >> (4 - q);
+                        if (q + 2 > lg0) re += n[q];
                     }
-                    run += n;
+                    n_re += (wave == 0 && lane == 0) ? (double)re : 0.0;
                 }
-                if (cls == 7) {
-                    const double fw = integrate_ray_wave<Real, 2>(R, myk, rd, rd2, nr, mytp, a.nside, a.zeta_g, split);
-                    if (lane == 0) fsum += fw;
-                    continue;
+                const int n_batch = nb[0] + nb[1] + nb[2] + nb[3] + nb[4] + nb[5];
+                for (int b = wave; b < n_batch; b += IW) {
+                    int cls = -1, bi = b;
+#pragma unroll
+                    for (int q = 5; q >= 0; --q)
+                        if (cls < 0) {
+                            if (bi < nb[q]) cls = q + 2;
+                            else bi -= nb[q];
+                        }
+                    const int ng = cls == 7 ? 1 : 64 >> cls;
+                    // this lane's ray: the (bi ng + lane / g)-th of the class
+                    const int want = bi * ng + (cls == 7 ? 0 : lane >> cls);
+                    int myk = -1, mytp = 0, run = 0;
+                    for (int base = 0; base < np && run < bi * ng + ng; base += 64) {
+                        int tp;
+                        const int c = ray_class(base + lane, tp);
+                        const uint64_t m = __ballot(c == cls);
+                        const int n = (int)__popcll(m), w = want - run;
+                        const bool mine = w >= 0 && w < n;
+                        const int pos = mine ? nth_set_bit(m, w) : 0;
+                        const int tv = __shfl(tp, pos, 64);
+                        if (mine) {
+                            myk = base + pos;
+                            mytp = tv;
+                        }
+                        run += n;
+                    }
+                    if (cls == 7) {
+                        const double fw = integrate_ray_wave<Real, 2>(R, myk, rd, rd2, nr, mytp, a.nside, a.zeta_g, split);
+                        if (lane == 0) fsum += fw;
+                        continue;
+                    }
+                    // the ray's mask, for its group's lanes to find their emitting points
+                    unsigned long long m0 = 0ull, m1 = 0ull;
+                    if (myk >= 0) {
+                        m0 = emask[(size_t)myk * ew];
+                        if (ew > 1) m1 = emask[(size_t)myk * ew + 1];
+                    }
+                    switch (cls) {
+                        case 2: march_batch<Real, 4>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                        case 3: march_batch<Real, 8>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                        case 4: march_batch<Real, 16>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                        case 5: march_batch<Real, 32>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                        default: march_batch<Real, 64>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+                    }
                 }
-                // the ray's mask, for its group's lanes to find their emitting points
-                unsigned long long m0 = 0ull, m1 = 0ull;
-                if (myk >= 0) {
-                    m0 = emask[(size_t)myk * ew];
-                    if (ew > 1) m1 = emask[(size_t)myk * ew + 1];
+            } else if (a.int_wave) {
+                // a wave per ray, the emitting rays dealt round robin over the waves
+                int seen = 0;
+                for (int base = 0; base < np; base += 64) {
+                    int t = 0;
+                    if (base + lane < np)
+                        t = mask_top(emask[(size_t)(base + lane) * ew], ew > 1 ? emask[(size_t)(base + lane) * ew + 1] : 0ull);
+                    uint64_t m = __ballot(t > 0);
+                    while (m) {
+                        const int l = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        if (seen % IW == wave) {
+                            const int tk = __builtin_amdgcn_readlane(t, l);
+                            const double f =
+                                nr > 64 ? integrate_ray_wave<Real, 2>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g, split)
+                                        : integrate_ray_wave<Real, 1>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g, split);
+                            if (lane == 0) fsum += f;
+                        }
+                        ++seen;
+                    }
                 }
-                switch (cls) {
-                    case 2: march_batch<Real, 4>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    case 3: march_batch<Real, 8>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    case 4: march_batch<Real, 16>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    case 5: march_batch<Real, 32>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
-                    default: march_batch<Real, 64>(a, R, myk, m0, m1, rcoef, rd, rd2, nr, split, fsum, cs_hi, cs_lo, n_f32, n_f64); break;
+            } else {
+                // a lane per ray: ray k on lane k % 64 of wave (k / 64) % IW
+                for (int k = wave * 64 + lane; k < np; k += 64 * IW) {
+                    const int t = mask_top(emask[(size_t)k * ew], ew > 1 ? emask[(size_t)k * ew + 1] : 0ull);
+                    if (t > 0) fsum += integrate_ray<Real>(R, k, rd, rd2, nr, t, a.nside, a.zeta_g, split);
                 }
             }
-        } else if (a.int_wave) {
-            // a wave per ray, the emitting rays dealt round robin over the waves
-            int seen = 0;
-            for (int base = 0; base < npix; base += 64) {
-                int t = 0;
-                if (base + lane < npix)
-                    t = mask_top(emask[(size_t)(base + lane) * ew], ew > 1 ? emask[(size_t)(base + lane) * ew + 1] : 0ull);
-                uint64_t m = __ballot(t > 0);
-                while (m) {
-                    const int l = __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1;
-                    if (seen % IW == wave) {
-                        const int tk = __builtin_amdgcn_readlane(t, l);
-                        const double f =
-                            nr > 64 ? integrate_ray_wave<Real, 2>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g, split)
-                                    : integrate_ray_wave<Real, 1>(R, base + l, rd, rd2, nr, tk, a.nside, a.zeta_g, split);
-                        if (lane == 0) fsum += f;
+            // the next target: claimed and walked into the other bank by the last wave
+            // (the node lists and that bank are not in use until the next barrier)
+            if (wave == WAVES - 1 && pass == npass - 1) {
+                int *const nsc = sc + (bank ^ 1) * S_COUNT;
+                if (lane == 0) {
+                    claim(nsc);
+                    nsc[S_PRE] = 1;
+                }
+                const int64_t nitem = uniform(lds_load(&nsc[S_ITEM]));
+                if (nitem < n_items) {
+                    const int64_t nit = FALLBACK ? (int64_t)a.ovf[nitem] : nitem;
+                    const int64_t ncell = a.targets ? a.targets[nit] : (int64_t)a.order[nit];
+                    if (ncell >= 0 && ncell < a.n_cells) {
+                        const int ndom = a.cell_dom[ncell];
+                        const int4 ng = a.geo[a.cell_node[ncell]];
+                        const int nsz = ng.w & kSizeMask;
+                        walk_target(a, a.doms[ndom].root, a.periodic ? a.doms[ndom].ext : nullptr, 2 * ng.x + nsz,
+                                    2 * ng.y + nsz, 2 * ng.z + nsz, fr0, fr1, acc, nsc, fmax, amax, n_test, FALLBACK);
+                        if (lane == 0) nsc[S_WALKED] = 1;
                     }
-                    ++seen;
                 }
             }
-        } else {
-            // a lane per ray: ray k on lane k % 64 of wave (k / 64) % IW
-            for (int k = wave * 64 + lane; k < npix; k += 64 * IW) {
-                const int t = mask_top(emask[(size_t)k * ew], ew > 1 ? emask[(size_t)k * ew + 1] : 0ull);
-                if (t > 0) fsum += integrate_ray<Real>(R, k, rd, rd2, nr, t, a.nside, a.zeta_g, split);
-            }
+            // the next pass re-initialises the buffers
+            if (pass + 1 < npass) __syncthreads();
         }
-        // the next target: claimed and walked into the other bank by the last wave
-        // (the node lists and that bank are not in use until the next barrier)
-        if (wave == WAVES - 1) {
-            int *const nsc = sc + (bank ^ 1) * S_COUNT;
-            if (lane == 0) {
-                claim(nsc);
-                nsc[S_PRE] = 1;
-            }
-            const int64_t nitem = uniform(lds_load(&nsc[S_ITEM]));
-            if (nitem < n_items) {
-                const int64_t nit = FALLBACK ? (int64_t)a.ovf[nitem] : nitem;
-                const int64_t ncell = a.targets ? a.targets[nit] : (int64_t)a.order[nit];
-                if (ncell >= 0 && ncell < a.n_cells) {
-                    const int ndom = a.cell_dom[ncell];
-                    const int4 ng = a.geo[a.cell_node[ncell]];
-                    const int nsz = ng.w & kSizeMask;
-                    walk_target(a, a.doms[ndom].root, a.periodic ? a.doms[ndom].ext : nullptr, 2 * ng.x + nsz,
-                                2 * ng.y + nsz, 2 * ng.z + nsz, fr0, fr1, acc, nsc, fmax, amax, n_test);
-                    if (lane == 0) nsc[S_WALKED] = 1;
-                }
-            }
-        }
+        if (overflowed) continue;
         fsum += (double)cs_hi + (double)cs_lo;
         fsum = wave_sum(fsum);
         if (lane == 0) red[wave] = fsum;
@@ -2366,6 +2404,7 @@ struct LaunchPlan {
     bool ldsbuf = true;
     bool cas = false;   // FP32 LDS buffers accumulated by compare-and-swap
     bool split = false; // A, E, V rows in LDS, emission rows in device memory
+    int pass_rays = 0;  // > 0: four rows per ray in LDS for this many rays at a time (passes)
     int intm = 1;   // integration: 1 a lane per ray, 2 a wave per ray, 3/4/5 a group of 4/8/16 lanes,
                     // 6/7/8 the same groups with the FP32 march (FP32 buffers only)
 };
@@ -2399,15 +2438,28 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     const int stride4 = 4 * nrm + 1, stride3 = 3 * nrm + 1;
     const bool fits4 = sweep_lds_bytes(real, npix, stride4, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
     const bool fits3 = f32 && !kv && sweep_lds_bytes(real, npix, stride3, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
-    if (bm == 1 && !fits4 && !fits3) return fail(c, TR_EINVAL, "ray buffers do not fit in LDS for this N_PIX and N_R");
-    L.ldsbuf = bm == 2 ? false : (fits4 || fits3);
-    L.split = L.ldsbuf && !fits4;
+    // else (FP64, or radial-kernel variants) four rows per ray in LDS for as many rays as fit, the
+    // target's rays mapped and integrated in passes over equal pixel ranges
+    int pass_rays = 0;
+    if (!fits4 && !fits3 && bm != 2) {
+        for (int r = npix - 1; r >= 16; --r)
+            if (sweep_lds_bytes(real, r, stride4, nrm, L.fmax, L.amax, waves, true) <= kLdsMax) {
+                const int n = (npix + r - 1) / r;
+                pass_rays = (npix + n - 1) / n;
+                break;
+            }
+    }
+    if (bm == 1 && !fits4 && !fits3 && pass_rays == 0)
+        return fail(c, TR_EINVAL, "ray buffers do not fit in LDS for this N_PIX and N_R");
+    L.ldsbuf = bm == 2 ? false : (fits4 || fits3 || pass_rays > 0);
+    L.split = L.ldsbuf && !fits4 && fits3;
+    L.pass_rays = L.ldsbuf && !fits4 && !fits3 ? pass_rays : 0;
     L.stride_k = L.split ? stride3 : stride4;
     if (!L.ldsbuf) {
         L.fmax = 1024;
         L.amax = 4096;
     }
-    L.lds = sweep_lds_bytes(real, npix, L.stride_k, nrm, L.fmax, L.amax, waves, L.ldsbuf);
+    L.lds = sweep_lds_bytes(real, L.pass_rays > 0 ? L.pass_rays : npix, L.stride_k, nrm, L.fmax, L.amax, waves, L.ldsbuf);
     if (kv) {
         L.fn = f32 ? pick_kernel_kv<float>(waves, L.ldsbuf, false) : pick_kernel_kv<double>(waves, L.ldsbuf, false);
         L.fn_fb = f32 ? pick_kernel_kv<float>(waves, L.ldsbuf, true) : pick_kernel_kv<double>(waves, L.ldsbuf, true);
@@ -2516,6 +2568,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     a.gbuf = c->gbuf;
     a.ebuf = c->ebuf;
     a.split = L.split ? 1 : 0;
+    a.pass_rays = L.pass_rays;
     a.theta2 = c->p.theta * c->p.theta;
     a.theta_if2 = c->p.theta_if > 0.0 ? c->p.theta_if * c->p.theta_if : 0.0;
     a.theta_src2 = c->p.theta_src > 0.0 ? c->p.theta_src * c->p.theta_src : 0.0;
@@ -2556,8 +2609,8 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     // the targets whose walk lists did not fit in LDS, again with lists in device memory
     // (one workgroup per compute unit; it ends at once when none was queued)
     {
-        const size_t lds = sweep_lds_bytes(c->p.precision == TR_FP32C ? 4 : 8, a.npix, L.stride_k, c->nr_max, 0, 0,
-                                           L.waves, L.ldsbuf);
+        const size_t lds = sweep_lds_bytes(c->p.precision == TR_FP32C ? 4 : 8, L.pass_rays > 0 ? L.pass_rays : a.npix,
+                                           L.stride_k, c->nr_max, 0, 0, L.waves, L.ldsbuf);
         hipLaunchKernelGGL(L.fn_fb, dim3(c->n_cu * std::min(L.per_cu, kFallbackPerCu)), dim3(L.waves * 64), lds,
                            c->stream, a);
     }
@@ -2568,7 +2621,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     }
     c->last_waves = L.waves;
     c->last_tpc = L.per_cu;
-    c->last_lds = L.ldsbuf ? (L.split ? 2 : 1) : 0;
+    c->last_lds = L.ldsbuf ? (L.split ? 2 : (L.pass_rays > 0 ? 3 : 1)) : 0;
     c->last_intw = lanes_per_ray(L.intm);
     c->last_int32 = L.intm >= 6 ? 1 : 0;
     c->last_cas = L.cas ? 1 : 0;

@@ -350,13 +350,15 @@ def test_long_walks_use_device_lists(T, orc):
 
 def test_few_targets_with_long_walks(T, orc):
     # a short target list whose walks all overflow the LDS lists, with ray
-    # buffers in device memory (FP64, FP32C) or split (FP32C at N_side 4 with
-    # 64 points): the second pass runs more workgroups than the first, each
-    # with its own buffer slab
+    # buffers in device memory (FP64, FP32C), split (FP32C at N_side 4 with
+    # 64 points) or in LDS in passes over the rays (FP64 at N_side 4): the
+    # second pass runs more workgroups than the first, each with its own
+    # buffer slab
     rng = np.random.default_rng(26)
     cases = [(W.small_lognormal(16, n_src=2, seed=25), T.TR_FP64, 2, 0),
              (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 2, 0),
-             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP32C, 1, 2)]
+             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP32C, 1, 2),
+             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP64, 1, 3)]
     for P, prec, buf, where in cases:
         tg = np.sort(rng.choice(P.total_cells(), 37, replace=False))
         f0, i0 = orc_sweep(orc, P, thin=True, targets=tg, theta=0.05)
@@ -469,7 +471,8 @@ def test_many_emitting_points(T, orc, prec):
 def test_split_ray_buffers(T, orc, waves):
     # N_side 4 with 64 radial points: four rows per ray (197 KB) do not fit in
     # LDS, three do, so the FP32C sweep keeps A, E, V in LDS and the emission
-    # rows in device memory; the FP64 sweep keeps everything in device memory
+    # rows in device memory; the FP64 sweep maps and integrates the rays in
+    # passes with LDS buffers, or keeps everything in device memory
     P = W.small_lognormal(16, n_src=6, seed=8, nside=4, n_radial=64)
     f0, i0 = orc_sweep(orc, P, thin=True)
     f1, i1 = orc_sweep(orc, P, f_prev=f0)
@@ -481,9 +484,13 @@ def test_split_ray_buffers(T, orc, waves):
         compare(g0, j0, f0, i0, TOL32, name=name + " thin")
         g1, j1, _ = gpu_sweep(T, P, T.TR_FP32C, f_prev=f0, launch=(waves, 0, 0, im, 0))
         compare(g1, j1, f1, i1, TOL32, front=front, name=name + " absorbing")
-    g1, j1, st = gpu_sweep(T, P, T.TR_FP64, f_prev=f0, launch=(waves, 0, 0, 0, 0))
-    assert st.buffer_in_lds == 0
-    compare(g1, j1, f1, i1, TOL64, name=f"fp64 waves {waves} device buffers")
+    # FP64: four rows per ray in LDS for a third of the rays at a time (passes),
+    # or all rows in device memory
+    for buf, where in ((0, 3), (2, 0)):
+        for im in (0, 1, 2):
+            g1, j1, st = gpu_sweep(T, P, T.TR_FP64, f_prev=f0, launch=(waves, 0, buf, im, 0))
+            assert st.buffer_in_lds == where
+            compare(g1, j1, f1, i1, TOL64, name=f"fp64 waves {waves} buffer {buf} integration {im}")
 
 
 @pytest.mark.parametrize("make", [lambda: W.small_lognormal(16, n_src=6, seed=31, nside=4, n_radial=48),
