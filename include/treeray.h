@@ -107,7 +107,8 @@ typedef struct {
     int32_t waves_per_target, targets_per_cu;   /* launch shape of the last sweep */
     int32_t buffer_in_lds;      /* where the last sweep kept its ray buffers: 1 LDS, 0 device memory,
                                    2 (FP32) the A, E, V rows in LDS and the emission rows in device memory,
-                                   3 LDS for part of the rays at a time (a target's rays in passes) */
+                                   3 LDS for part of the rays at a time (a target's rays in passes; the
+                                   emission rows in device memory when that saves a pass) */
     int32_t overflow;           /* nonzero if a walk list overflowed */
     int32_t integration_wave;   /* lanes that integrated one ray in the last sweep: 1, 4, 8, 16 or 64 */
     int32_t lds_cas;            /* 1 if the last sweep accumulated its LDS ray buffers by compare-and-swap */

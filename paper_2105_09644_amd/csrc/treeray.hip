@@ -2438,22 +2438,29 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     const int stride4 = 4 * nrm + 1, stride3 = 3 * nrm + 1;
     const bool fits4 = sweep_lds_bytes(real, npix, stride4, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
     const bool fits3 = f32 && !kv && sweep_lds_bytes(real, npix, stride3, nrm, L.fmax, L.amax, waves, true) <= kLdsMax;
-    // else (FP64, or radial-kernel variants) four rows per ray in LDS for as many rays as fit, the
-    // target's rays mapped and integrated in passes over equal pixel ranges
+    // else (FP64, or radial-kernel variants) the rays in LDS for as many as fit, with four rows
+    // per ray or (fewer passes) the split rows, a target's rays mapped and integrated in
+    // passes over equal pixel ranges
     int pass_rays = 0;
+    bool pass_split = false;
     if (!fits4 && !fits3 && bm != 2) {
-        for (int r = npix - 1; r >= 16; --r)
-            if (sweep_lds_bytes(real, r, stride4, nrm, L.fmax, L.amax, waves, true) <= kLdsMax) {
-                const int n = (npix + r - 1) / r;
-                pass_rays = (npix + n - 1) / n;
-                break;
-            }
+        auto passes = [&](int stride) {   // passes of the largest ray count that fits (0: none)
+            for (int r = npix - 1; r >= 16; --r)
+                if (sweep_lds_bytes(real, r, stride, nrm, L.fmax, L.amax, waves, true) <= kLdsMax) return (npix + r - 1) / r;
+            return 0;
+        };
+        const int n4 = passes(stride4), n3 = kv ? 0 : passes(stride3);
+        const int n = n3 > 0 && (n4 == 0 || n3 < n4) ? n3 : n4;
+        if (n > 0) {
+            pass_rays = (npix + n - 1) / n;
+            pass_split = n == n3 && n3 != n4;
+        }
     }
     if (bm == 1 && !fits4 && !fits3 && pass_rays == 0)
         return fail(c, TR_EINVAL, "ray buffers do not fit in LDS for this N_PIX and N_R");
     L.ldsbuf = bm == 2 ? false : (fits4 || fits3 || pass_rays > 0);
-    L.split = L.ldsbuf && !fits4 && fits3;
     L.pass_rays = L.ldsbuf && !fits4 && !fits3 ? pass_rays : 0;
+    L.split = L.ldsbuf && !fits4 && (fits3 || (L.pass_rays > 0 && pass_split));
     L.stride_k = L.split ? stride3 : stride4;
     if (!L.ldsbuf) {
         L.fmax = 1024;
@@ -2621,7 +2628,7 @@ tr_status launch_sweep(tr_ctx *c, const int64_t *targets, int64_t n, double *f_o
     }
     c->last_waves = L.waves;
     c->last_tpc = L.per_cu;
-    c->last_lds = L.ldsbuf ? (L.split ? 2 : (L.pass_rays > 0 ? 3 : 1)) : 0;
+    c->last_lds = L.ldsbuf ? (L.pass_rays > 0 ? 3 : (L.split ? 2 : 1)) : 0;
     c->last_intw = lanes_per_ray(L.intm);
     c->last_int32 = L.intm >= 6 ? 1 : 0;
     c->last_cas = L.cas ? 1 : 0;
