@@ -1080,7 +1080,7 @@ __device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, 
 // The evaluation points are r_i = c i^2; the per-node loop recomputes them
 // in registers, so it makes no memory round trip besides its atomics.
 // KV: the radial-kernel variants of App. A (otherwise two-point W_f,3 and W_p)
-template <typename Real, int ATOMIC, bool KV>
+template <typename Real, int ATOMIC, bool KV, bool PASS>
 __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned long long *emask, int ew, const int *per,
                           const Real *rt, int nr,
                           Real rc_inv,
@@ -1253,7 +1253,7 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
         const int this_kc = next_kc;
         next_kc = fetch_kc(j + 1);
         if (jt >= 0) {
-            if (np == a.npix) {
+            if (!PASS) {
                 nd = jt & 127;
                 if (lane < nd) slot_kc = this_kc;
             } else {
@@ -1299,7 +1299,7 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
                 const uint64_t m = __ballot(pix == k) & rem;
                 rem &= ~m;
                 // (a pass keeps its own pixels, as local ray indices)
-                if ((unsigned)(k - k0) < (unsigned)np) {
+                if (!PASS || (unsigned)(k - k0) < (unsigned)np) {
                     const int kc = (k - k0) | ((int)__popcll(m) << 16);   // uniform
                     slot_kc = lane == nd ? kc : slot_kc;
                     ++nd;
@@ -1495,7 +1495,7 @@ __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx
 
 // The sweep of one launch.  FALLBACK: the second pass over the items whose
 // walk lists did not fit in LDS, with the lists in device memory.
-template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK, bool KV, bool CAS = false>
+template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK, bool KV, bool CAS = false, bool PASS = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     using R4 = typename R4T<Real>::T;
@@ -1506,8 +1506,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar loops over waves' work
     const int nrm = a.nr_max, npix = a.npix;
     // rays held at once (all of them, or a.pass_rays per pass)
-    const int prays = a.pass_rays > 0 ? a.pass_rays : npix;
-    const int npass = (npix + prays - 1) / prays;
+    const int prays = PASS && a.pass_rays > 0 ? a.pass_rays : npix;
+    const int npass = PASS ? (npix + prays - 1) / prays : 1;
     const size_t buf_elems = (size_t)prays * a.stride_k;
     char *p = smem;
     Real *buf;
@@ -1633,12 +1633,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             cached_dom = dom;
             cached_tsize = tsize;
         }
-        double fsum = 0.0;
-        float cs_hi = 0.0f, cs_lo = 0.0f;   // compensated FP32 sum of this lane's FP32-marched rays
-        bool overflowed = false;
-        // the rays in passes of prays consecutive pixels (one pass when all fit)
-        for (int pass = 0; pass < npass; ++pass) {
-            const int k0 = pass * prays, np = min(prays, npix - k0);
+        double ftarget = 0.0;   // this lane's share of the target's flux over the passes
+        // The rays k0 .. k0 + np - 1: all of them, or (PASS) one pass of prays
+        // consecutive pixels at a time, the passes looping back here (a target
+        // whose walk overflows leaves with continue).  Without passes there is
+        // no loop, so the body compiles as straight-line code.
+        int pass = 0;
+    next_pass:
+        {
+            const int k0 = pass * prays, np = PASS ? min(prays, npix - k0) : npix;
             // ray buffer: zero emission, the target's own share of A, E, V
             {
                 // every ray starts from the same 4 (split: 3) N_R values: lane l holds entries l + 64 m
@@ -1703,7 +1706,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 }
                 end = uniform(end);
                 if (end <= start) break;
-                map_nodes<Real, ATOMIC, KV>(a, R, emask, ew, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
+                map_nodes<Real, ATOMIC, KV, PASS>(a, R, emask, ew, per, rt, nr, rc_inv, rcoef, acc + start, end - start, tx, ty, tz,
                                             tsize, k0, np, n_guard, n_tab);
             }
             __syncthreads();
@@ -1726,14 +1729,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                         atomicOr(&a.queue[1], 1);
                     }
                 }
-                overflowed = true;
-                break;
+                continue;
             }
             if (pass == 0) n_acc += (wave == 0 && lane == 0) ? (double)scb[S_TOTAL] : 0.0;
 
             // --- per-ray integration and the sum over rays (rays without emission give 0),
             // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
             constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
+            double fsum = 0.0;
+            float cs_hi = 0.0f, cs_lo = 0.0f;   // compensated FP32 sum of this lane's FP32-marched rays
             if (wave >= IW) {
                 // no rays here
             } else if (a.int_group > 0) {
@@ -1867,12 +1871,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     }
                 }
             }
-            // the next pass re-initialises the buffers
-            if (pass + 1 < npass) __syncthreads();
+            ftarget += fsum + ((double)cs_hi + (double)cs_lo);
         }
-        if (overflowed) continue;
-        fsum += (double)cs_hi + (double)cs_lo;
-        fsum = wave_sum(fsum);
+        if (PASS && ++pass < npass) {
+            __syncthreads();   // the next pass re-initialises the buffers
+            goto next_pass;
+        }
+        const double fsum = wave_sum(ftarget);
         if (lane == 0) red[wave] = fsum;
         __syncthreads();
         if (tid == 0) {
@@ -1939,6 +1944,18 @@ template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_cas_fallback(SweepArgs a)
 {
     sweep_body<float, WAVES, true, true, false, true>(a);
+}
+
+// LDS ray buffers for part of a target's rays at a time (passes)
+template <typename Real, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_pass(SweepArgs a)
+{
+    sweep_body<Real, WAVES, true, false, false, false, true>(a);
+}
+template <typename Real, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_sweep_pass_fallback(SweepArgs a)
+{
+    sweep_body<Real, WAVES, true, true, false, false, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -2371,6 +2388,15 @@ KernelFn pick_kernel_kv(int waves, bool ldsbuf, bool fallback)
     return nullptr;
 }
 
+template <typename Real>
+KernelFn pick_kernel_pass(int waves, bool fallback)
+{
+    if (waves == 4) return fallback ? (KernelFn)k_sweep_pass_fallback<Real, 4> : (KernelFn)k_sweep_pass<Real, 4>;
+    if (waves == 8) return fallback ? (KernelFn)k_sweep_pass_fallback<Real, 8> : (KernelFn)k_sweep_pass<Real, 8>;
+    if (waves == 16) return fallback ? (KernelFn)k_sweep_pass_fallback<Real, 16> : (KernelFn)k_sweep_pass<Real, 16>;
+    return nullptr;
+}
+
 KernelFn pick_kernel_cas(int waves, bool fallback)
 {
     if (waves == 8) return fallback ? (KernelFn)k_sweep_cas_fallback<8> : (KernelFn)k_sweep_cas<8>;
@@ -2443,7 +2469,7 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     // passes over equal pixel ranges
     int pass_rays = 0;
     bool pass_split = false;
-    if (!fits4 && !fits3 && bm != 2) {
+    if (!fits4 && !fits3 && bm != 2 && !kv && (waves == 4 || waves == 8 || waves == 16)) {
         auto passes = [&](int stride) {   // passes of the largest ray count that fits (0: none)
             for (int r = npix - 1; r >= 16; --r)
                 if (sweep_lds_bytes(real, r, stride, nrm, L.fmax, L.amax, waves, true) <= kLdsMax) return (npix + r - 1) / r;
@@ -2478,11 +2504,15 @@ tr_status plan_sweep(tr_ctx *c, int64_t n_items, int waves_req, int tpc_req, int
     // accumulation: compare-and-swap by default (FP32, LDS, 8 or 16 waves)
     {
         const int am = atom_req > 0 ? atom_req : (c->atommode > 0 ? c->atommode : c->tuned_atom[f32 ? 1 : 0]);
-        L.cas = f32 && L.ldsbuf && !kv && (waves == 8 || waves == 16) && (am > 0 ? am == 2 : true);
+        L.cas = f32 && L.ldsbuf && !kv && L.pass_rays == 0 && (waves == 8 || waves == 16) && (am > 0 ? am == 2 : true);
         if (L.cas) {
             L.fn = pick_kernel_cas(waves, false);
             L.fn_fb = pick_kernel_cas(waves, true);
         }
+    }
+    if (L.pass_rays > 0) {   // (hardware atomics)
+        L.fn = f32 ? pick_kernel_pass<float>(waves, false) : pick_kernel_pass<double>(waves, false);
+        L.fn_fb = f32 ? pick_kernel_pass<float>(waves, true) : pick_kernel_pass<double>(waves, true);
     }
     HIPCHK(hipFuncSetAttribute((const void *)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
     HIPCHK(hipFuncSetAttribute((const void *)L.fn_fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));

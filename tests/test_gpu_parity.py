@@ -545,17 +545,25 @@ def test_errors(T):
         ctx.sync()
     assert e.value.status == T.TR_EINVAL
     assert math.isnan(o[2].item()) and o[0].item() > 0
-    # launch options out of range; buffers that cannot fit in LDS at this size
+    # launch options out of range
     for bad_launch in ((3, 0, 0, 0, 0), (4, -1, 0, 0, 0), (4, 0, 3, 0, 0), (4, 0, 0, 9, 0), (4, 0, 0, 0, 3)):
         with pytest.raises(T.TreeRayError) as e:
             ctx.set_launch(*bad_launch)
         assert e.value.status == T.TR_EINVAL
     ctx.close()
-    big = W.small_uniform(16, nside=8, n_radial=64)   # 768 rays of 64 points: 590 KB in FP64
-    ctx = T.context_for(big, T.TR_FP64)
-    ctx.set_launch(4, 0, 1, 0, 0)
-    ctx.build(torch.tensor(big.n_h[0], device="cuda"), thin=True)
-    with pytest.raises(T.TreeRayError) as e:
-        ctx.sweep(torch.zeros(ctx.n_cells, dtype=torch.float64, device="cuda"))
-    assert e.value.status == T.TR_EINVAL and "LDS" in str(e.value)
-    ctx.close()
+
+
+def test_many_ray_passes(T, orc):
+    # N_side 8 with 64 points in FP64: 768 rays of four rows (1.6 MB) are
+    # mapped and integrated in passes of a few dozen rays held in LDS
+    P = W.small_lognormal(16, n_src=3, seed=44, nside=8, n_radial=64)
+    rng = np.random.default_rng(45)
+    tg = np.sort(rng.choice(P.total_cells(), 96, replace=False))
+    f0, i0 = orc_sweep(orc, P, thin=True, targets=tg)
+    f1, i1 = orc_sweep(orc, P, f_prev=None, targets=tg)
+    for waves in (4, 16):
+        g0, j0, st = gpu_sweep(T, P, T.TR_FP64, thin=True, targets=tg, launch=(waves, 0, 1, 0, 0))
+        assert st.buffer_in_lds == 3
+        compare(g0, j0, f0, i0, TOL64, name=f"N_side 8 passes waves {waves} thin")
+        g1, j1, _ = gpu_sweep(T, P, T.TR_FP64, targets=tg, launch=(waves, 0, 1, 0, 0))
+        compare(g1, j1, f1, i1, TOL64, name=f"N_side 8 passes waves {waves} absorbing")
