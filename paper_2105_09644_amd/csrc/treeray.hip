@@ -939,6 +939,21 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, unsigne
     if (clear_eps && act && j > 0 && !near) R.eps(k, j) = 0.0f;
 }
 
+// The class of ray k (k >= np: none) from its mask of emitting points: 0 no
+// emission, else ceil(log2) of its number of emitting points, at least lg0, 7
+// beyond 64; tp returns its outermost emitting point.
+__device__ inline int ray_class(const unsigned long long *emask, int ew, int np, int lg0, int k, int &tp)
+{
+    unsigned long long w0 = 0ull, w1 = 0ull;
+    if (k < np) {
+        w0 = emask[(size_t)k * ew];
+        if (ew > 1) w1 = emask[(size_t)k * ew + 1];
+    }
+    tp = mask_top(w0, w1);
+    const int cnt = (int)(__popcll(w0) + __popcll(w1));
+    return cnt == 0 ? 0 : cnt > 64 ? 7 : max(lg0, 32 - __clz(cnt - 1));
+}
+
 // One batch of the group integration: 64 / G rays of G lanes each (myk < 0:
 // no ray on this group; (m0, m1) the ray's mask of emitting points).  Adds the
 // rays' F_{0,k} on their groups' first lanes: FP64 results into fsum, FP32
@@ -1080,6 +1095,13 @@ __device__ inline Real emission_weight(int mode, int i, int io, int le, int ne, 
 // The evaluation points are r_i = c i^2; the per-node loop recomputes them
 // in registers, so it makes no memory round trip besides its atomics.
 // KV: the radial-kernel variants of App. A (otherwise two-point W_f,3 and W_p)
+// This lane's (pixel, count) pair of the angular-table entry t ((first << 7) |
+// pairs; t < 0: none), 0 beyond the entry's pairs
+__device__ inline int table_pairs(const int32_t *pool, int t, int lane)
+{
+    return t >= 0 && lane < (t & 127) ? pool[(t >> 7) + lane] : 0;
+}
+
 template <typename Real, int ATOMIC, bool KV, bool PASS>
 __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned long long *emask, int ew, const int *per,
                           const Real *rt, int nr,
@@ -1238,11 +1260,7 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
     const float ox = 0.5f * (float)(2 * bx - tx), oy = 0.5f * (float)(2 * by - ty), oz = 0.5f * (float)(2 * bz - tz);
     const float sx = (float)ex * inv_s, sy = (float)ey * inv_s, sz = (float)ez * inv_s;
     // the table entries of the next node are fetched while one is mapped
-    auto fetch_kc = [&](int jj) -> int {
-        const int t = jj < cnt ? rdlane(tab, jj) : -1;
-        return t >= 0 && lane < (t & 127) ? a.atab_pool[(t >> 7) + lane] : 0;
-    };
-    int next_kc = fetch_kc(0);
+    int next_kc = table_pairs(a.atab_pool, cnt > 0 ? rdlane(tab, 0) : -1, lane);
     for (int j = 0; j < cnt; ++j) {
         // --- angular: slot q (lane q of slot_kc) holds the q-th distinct pixel
         // and its sub-point count (pixel < 2^16, count <= 64), packed so that one
@@ -1251,7 +1269,7 @@ __device__ void map_nodes(const SweepArgs &a, const RayRows<Real> &R, unsigned l
         int nd = 0, slot_kc = 0;
         const int jt = rdlane(tab, j);
         const int this_kc = next_kc;
-        next_kc = fetch_kc(j + 1);
+        next_kc = table_pairs(a.atab_pool, j + 1 < cnt ? rdlane(tab, j + 1) : -1, lane);
         if (jt >= 0) {
             if (!PASS) {
                 nd = jt & 127;
@@ -1748,22 +1766,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 // class first and pixel order within a class, are dealt round robin
                 // over the waves.
                 const int lg0 = 31 - __clz(a.int_group);
-                auto ray_class = [&](int k, int &tp) -> int {   // 0: no emission
-                    unsigned long long w0 = 0ull, w1 = 0ull;
-                    if (k < np) {
-                        w0 = emask[(size_t)k * ew];
-                        if (ew > 1) w1 = emask[(size_t)k * ew + 1];
-                    }
-                    tp = mask_top(w0, w1);
-                    const int cnt = (int)(__popcll(w0) + __popcll(w1));
-                    return cnt == 0 ? 0 : cnt > 64 ? 7 : max(lg0, 32 - __clz(cnt - 1));   // ceil(log2 cnt)
-                };
                 int nb[6];   // batches of classes 2 .. 7 (class 7: a ray each)
                 {
                     int n[6] = {0, 0, 0, 0, 0, 0};
                     for (int base = 0; base < np; base += 64) {
                         int tp;
-                        const int c = ray_class(base + lane, tp);
+                        const int c = ray_class(emask, ew, np, lg0, base + lane, tp);
 #pragma unroll
                         for (int q = 0; q < 6; ++q) n[q] += (int)__popcll(__ballot(c == q + 2));
                     }
@@ -1790,7 +1798,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     int myk = -1, mytp = 0, run = 0;
                     for (int base = 0; base < np && run < bi * ng + ng; base += 64) {
                         int tp;
-                        const int c = ray_class(base + lane, tp);
+                        const int c = ray_class(emask, ew, np, lg0, base + lane, tp);
                         const uint64_t m = __ballot(c == cls);
                         const int n = (int)__popcll(m), w = want - run;
                         const bool mine = w >= 0 && w < n;
