@@ -829,8 +829,9 @@ __device__ double integrate_rays_group(const RayRows<Real> &R, int k, unsigned l
 //  - radial differences from exact integers: r_j - r_i = c (j^2 - i^2), so a
 //    segment's volume dV_{i,j} carries no cancellation error;
 //  - Phi_j is kept as an unevaluated FP32 pair (hi + lo): each loss R is
-//    subtracted by TwoSum, so Phi's error is only that of the R's themselves
-//    (a few ulp of each, at most a few 1e-7 of the emitted Phi_jj in all);
+//    subtracted with its rounding error kept (Fast2Sum, exact while R <= Phi),
+//    so Phi's error is only that of the R's themselves (a few ulp of each, at
+//    most a few 1e-7 of the emitted Phi_jj in all);
 //  - F_{0,k} = sum_j Phi_{0,j} / r_j^2 as a compensated group sum.
 // Where the FP32 result is not safe to 1e-4 -- a live source whose Phi falls
 // below front_ratio of its emitted Phi_jj, or dies in a step whose loss is
@@ -864,6 +865,7 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, unsigne
         rj = rcoef * (float)j2;
     }
     const float phjj = epsj * inv4pi;   // Phi_jj, emitted at r_j
+    const float gz = ns * i2rj;         // zeta_g = min(1, gz (r_j - r_i))
     float ph = 0.0f, pl = 0.0f, a1 = 0.0f, fb1 = 0.0f;
     bool live = false, died = false;
     float bd = 0.0f, ld = 0.0f;   // at the source's death: its Phi before the step and the step's loss
@@ -896,11 +898,14 @@ __device__ void integrate_rays_group_f32(const RayRows<float> &R, int k, unsigne
             const float g = fminf(2.0f * __builtin_amdgcn_rcpf(ftot), __builtin_amdgcn_rcpf(fb1));
             const float aseg = 0.5f * (ai + a1) * (rcoef * odd) * third;
             float z = far ? f * g : 1.0f;
-            if (zeta_g) z *= fminf(1.0f, ns * A * i2rj);
+            if (zeta_g) z *= fminf(1.0f, A * gz);
             const float loss = aseg * (A2 + A * Bv + B2) * z;
             const float before = ph + pl;
-            float sh, se;
-            two_sum(ph, -loss, sh, se);
+            // ph - loss as sh + se, exactly while the source lives (|loss| <= ph:
+            // Fast2Sum); a larger loss kills it whatever the rounding, and a near
+            // tie is the close call marched again in FP64
+            const float sh = ph - loss;
+            const float se = -loss - (sh - ph);
             const float npl = pl + se;
             const bool alive = live && sh + npl > 0.0f;
             const bool dies = live && !alive;
