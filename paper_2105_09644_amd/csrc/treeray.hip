@@ -1430,7 +1430,10 @@ __device__ inline void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATO
 // the other waves map them while the walk goes on.
 // S_PRE: the bank's item was claimed (and possibly walked, S_WALKED) ahead,
 // during the previous target's integration
-enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_PRE, S_WALKED, S_COUNT = 16 };
+enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_PRE, S_WALKED,
+       // a walk by two waves: the claim's generation, their meetings, the next
+       // frontier's length (three by level), the accepted count, an overflow
+       S_PGEN, S_PMEET, S_PNEXT, S_PACC = S_PNEXT + 3, S_POVF, S_COUNT = 16 };
 
 // Waits until this wave's device-memory stores have completed (vmcnt 0), so
 // that an LDS flag written next publishes them to the workgroup's other waves
@@ -1516,6 +1519,103 @@ __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx
     }
 }
 
+// The same walk by two waves (half 0 and 1) of one workgroup, into a list that
+// is read only once the walk is done: the batches of a level alternate
+// between the waves, their appends to the next frontier and to the accepted
+// list are reserved by LDS atomics, and the waves meet at an LDS counter after
+// every level (both leave the loop at the same level).  sc[S_PMEET],
+// sc[S_PNEXT], sc[S_PACC], sc[S_POVF] and cur[0] = root are set by half 0
+// before either starts.  Half 0 publishes the list.
+__device__ void walk_target_pair(const SweepArgs &a, int half, const int *per, int tx, int ty, int tz, int *fr0,
+                                 int *fr1, int *acc, int *sc, int fmax, int amax, double &n_test, bool dev_lists)
+{
+    const int lane = lane_id();
+    int *cur = fr0, *nxt = fr1;
+    int nfr = 1;
+    for (int lev = 0;; ++lev) {
+        int *const next_count = &sc[S_PNEXT + lev % 3];
+        // the counter of the level after next is free (read before the last meeting)
+        if (half == 0 && lane == 0) sc[S_PNEXT + (lev + 1) % 3] = 0;
+        for (int base = 64 * half; base < nfr; base += 128) {
+            const int idx = base + lane;
+            const bool valid = idx < nfr;
+            int n = 0, nch = 0, fc = 0;
+            bool acc_it = false;
+            if (valid) {
+                n = cur[idx];
+                const int4 g = a.geo[n];
+                const int2 tp = a.topo[n];
+                const int sz = g.w & kSizeMask;
+                const bool leaf = tp.y == 0;
+                const bool inside = (2 * g.x <= tx && tx < 2 * (g.x + sz)) && (2 * g.y <= ty && ty < 2 * (g.y + sz)) &&
+                                    (2 * g.z <= tz && tz < 2 * (g.z + sz));
+                bool open_it = false;
+                if (inside) {
+                    open_it = !leaf;
+                } else if (leaf) {
+                    acc_it = true;
+                } else {
+                    int vx = 2 * g.x + sz - tx, vy = 2 * g.y + sz - ty, vz = 2 * g.z + sz - tz;
+                    if (per) {
+                        vx += 2 * nearest_copy_shift(vx, per[0]);
+                        vy += 2 * nearest_copy_shift(vy, per[1]);
+                        vz += 2 * nearest_copy_shift(vz, per[2]);
+                    }
+                    const double ddx = (double)vx, ddy = (double)vy, ddz = (double)vz;
+                    const double D2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                    double th2 = a.theta2;   // lowered by the IF and Src MACs (Sec. 2.4)
+                    if ((g.w & kIfBit) && a.theta_if2 > 0.0) th2 = fmin(th2, a.theta_if2);
+                    if ((g.w & kSrcBit) && a.theta_src2 > 0.0) th2 = fmin(th2, a.theta_src2);
+                    acc_it = th2 * D2 > 4.0 * (double)sz * (double)sz;
+                    open_it = !acc_it;
+                }
+                nch = open_it ? tp.y : 0;
+                fc = tp.x;
+            }
+            n_test += valid ? 1.0 : 0.0;
+            const uint64_t macc = __ballot(acc_it);
+            const int cacc = __popcll(macc);
+            int tot = 0;
+            const int off = wave_excl_scan_dpp(nch, tot);
+            int oa = 0, on = 0;
+            if (lane == 0) {
+                oa = cacc ? atomicAdd(&sc[S_PACC], cacc) : 0;
+                on = tot ? atomicAdd(next_count, tot) : 0;
+            }
+            oa = __shfl(oa, 0, 64);
+            on = __shfl(on, 0, 64);
+            if (oa + cacc > amax || on + tot > fmax) {
+                // nothing is written; both waves stop after this level's meeting
+                if (lane == 0) sc[S_POVF] = lev + 1;
+                continue;
+            }
+            if (acc_it) acc[oa + __popcll(macc & ((1ull << lane) - 1ull))] = n;
+            for (int c = 0; c < nch; ++c) nxt[on + off + c] = fc + c;
+        }
+        // meet the other wave: the level's appends are all written
+        if (dev_lists) wait_stores();
+        if (lane == 0) atomicAdd(&sc[S_PMEET], 1);
+        while (lds_load(&sc[S_PMEET]) < 2 * (lev + 1)) __builtin_amdgcn_s_sleep(1);
+        nfr = uniform(lds_load(next_count));
+        // (an overflow of the other wave's next level is not this level's)
+        const int ov = uniform(lds_load(&sc[S_POVF]));
+        if (nfr == 0 || (ov != 0 && ov <= lev + 1)) break;
+        int *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (half == 0 && lane == 0) {
+        // after an overflow the list has gaps: nothing is mapped (the target
+        // goes to the second pass)
+        const bool ovf = lds_load(&sc[S_POVF]) != 0;
+        sc[S_TOTAL] = ovf ? 0 : lds_load(&sc[S_PACC]);
+        if (ovf) sc[S_OVF] = 1;
+        lds_store(&sc[S_AVAIL], sc[S_TOTAL]);
+        lds_store(&sc[S_DONE], 1);
+        sc[S_WALKED] = 1;
+    }
+}
+
 // The sweep of one launch.  FALLBACK: the second pass over the items whose
 // walk lists did not fit in LDS, with the lists in device memory.
 template <typename Real, int WAVES, bool LDSBUF, bool FALLBACK, bool KV, bool CAS = false, bool PASS = false>
@@ -1594,11 +1694,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         b[S_TOTAL] = 0;
         b[S_WALKED] = 0;
     };
-    if (tid == 0) sc[S_PRE] = sc[S_COUNT + S_PRE] = 0;
+    if (tid == 0) {
+        sc[S_PRE] = sc[S_COUNT + S_PRE] = 0;
+        sc[S_PGEN] = sc[S_COUNT + S_PGEN] = 0;   // (generations start at 1)
+    }
     int bank = 0;
+    int titer = 0;   // targets begun by this workgroup (the generation of a paired walk's claim)
     int cached_dom = -1, cached_tsize = -1;   // whose radial tables the LDS holds
     for (;;) {
         int *const scb = sc + bank * S_COUNT;
+        ++titer;
         __syncthreads();
         if (tid == 0) {
             if (!scb[S_PRE]) claim(scb);
@@ -1758,7 +1863,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 
             // --- per-ray integration and the sum over rays (rays without emission give 0),
             // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
-            constexpr int IW = WAVES > 1 ? WAVES - 1 : 1;
+            // (at 16 waves the last two walk the next target, else the last one: with
+            // fewer waves one more integrating wave is worth more than a faster walk)
+            constexpr bool kPair = WAVES >= 16;
+            constexpr int IW = kPair ? WAVES - 2 : (WAVES > 1 ? WAVES - 1 : 1);
             double fsum = 0.0;
             float cs_hi = 0.0f, cs_lo = 0.0f;   // compensated FP32 sum of this lane's FP32-marched rays
             if (wave >= IW) {
@@ -1862,26 +1970,58 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     if (t > 0) fsum += integrate_ray<Real>(R, k, rd, rd2, nr, t, a.nside, a.zeta_g, split);
                 }
             }
-            // the next target: claimed and walked into the other bank by the last wave
-            // (the node lists and that bank are not in use until the next barrier)
-            if (wave == WAVES - 1 && pass == npass - 1) {
+            // the next target: claimed and walked into the other bank by the last
+            // wave, or the last two (the node lists and that bank are not in use
+            // until the next barrier)
+            if ((kPair ? wave >= WAVES - 2 : wave == WAVES - 1) && pass == npass - 1) {
                 int *const nsc = sc + (bank ^ 1) * S_COUNT;
-                if (lane == 0) {
-                    claim(nsc);
-                    nsc[S_PRE] = 1;
+                const int half = WAVES - 1 - wave;
+                if (half == 0) {
+                    if (lane == 0) {
+                        claim(nsc);
+                        nsc[S_PRE] = 1;
+                    }
+                } else {
+                    // the other wave's claim of this generation
+                    while (lds_load(&nsc[S_PGEN]) != titer) __builtin_amdgcn_s_sleep(1);
                 }
                 const int64_t nitem = uniform(lds_load(&nsc[S_ITEM]));
+                bool walk = false;
+                int ndom = 0, ntx = 0, nty = 0, ntz = 0;
                 if (nitem < n_items) {
                     const int64_t nit = FALLBACK ? (int64_t)a.ovf[nitem] : nitem;
                     const int64_t ncell = a.targets ? a.targets[nit] : (int64_t)a.order[nit];
                     if (ncell >= 0 && ncell < a.n_cells) {
-                        const int ndom = a.cell_dom[ncell];
+                        walk = true;
+                        ndom = a.cell_dom[ncell];
                         const int4 ng = a.geo[a.cell_node[ncell]];
                         const int nsz = ng.w & kSizeMask;
-                        walk_target(a, a.doms[ndom].root, a.periodic ? a.doms[ndom].ext : nullptr, 2 * ng.x + nsz,
-                                    2 * ng.y + nsz, 2 * ng.z + nsz, fr0, fr1, acc, nsc, fmax, amax, n_test, FALLBACK);
+                        ntx = 2 * ng.x + nsz;
+                        nty = 2 * ng.y + nsz;
+                        ntz = 2 * ng.z + nsz;
+                    }
+                }
+                const int *nper = a.periodic ? a.doms[ndom].ext : nullptr;
+                if (!kPair) {
+                    if (walk) {
+                        walk_target(a, a.doms[ndom].root, nper, ntx, nty, ntz, fr0, fr1, acc, nsc, fmax, amax, n_test,
+                                    FALLBACK);
                         if (lane == 0) nsc[S_WALKED] = 1;
                     }
+                } else {
+                    if (half == 0) {
+                        if (lane == 0) {
+                            nsc[S_PMEET] = 0;
+                            nsc[S_PNEXT] = 0;
+                            nsc[S_PACC] = 0;
+                            nsc[S_POVF] = 0;
+                            if (walk) fr0[0] = a.doms[ndom].root;
+                        }
+                        if (FALLBACK) wait_stores();   // (fr0 in device memory)
+                        if (lane == 0) lds_store(&nsc[S_PGEN], titer);
+                    }
+                    if (walk)
+                        walk_target_pair(a, half, nper, ntx, nty, ntz, fr0, fr1, acc, nsc, fmax, amax, n_test, FALLBACK);
                 }
             }
             ftarget += fsum + ((double)cs_hi + (double)cs_lo);
