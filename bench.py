@@ -275,7 +275,8 @@ def main():
         fname = "fp32c" if form == "f32" else "fp64"
         traffic = measured_traffic(P.name, fname, r["launch"], digest)
         cnt = measured_counters(P.name, fname, r["launch"], digest)
-        kernel = "k_sweep_cas" if r["cas"] else "k_sweep"   # the instantiation that ran
+        # the instantiation that ran (buffer place 3: LDS ray buffers in passes)
+        kernel = "k_sweep_cas" if r["cas"] else ("k_sweep_pass" if r["lds"] == 3 else "k_sweep")
         occ = r["per_cu"] * r["waves"] / 4.0                 # resident waves per SIMD
         alu = {"bound": "alu", "achieved": round(flops / sec / 1e12, 3), "peak": VALU_PEAK_TFLOPS[form],
                "unit": "TFLOP/s", "frac": round(flops / sec / 1e12 / VALU_PEAK_TFLOPS[form], 4),
