@@ -49,7 +49,7 @@ METRIC = "target-cell·ray updates/s, FP32-compensated vs FP64, at ≤1e-4 rel f
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
-# Algorithmic work per unit (the traversal model of the hot-path survey):
+# Algorithmic work per unit (a traversal model of the sweep):
 #   per accepted node 40 FLOP per angular sub-point (s^3 of them), 80 for the
 #   radial weights and 60 for the accumulation into the ray buffer;
 #   per tested node its FP32 record (com 12 B, eps/alpha/E/V 16 B, topology
@@ -154,7 +154,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU sharding is described in DESIGN.md and not built.", file=sys.stderr)
+              "sharding the targets over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
