@@ -1431,7 +1431,7 @@ __device__ inline void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATO
 // S_PRE: the bank's item was claimed (and possibly walked, S_WALKED) ahead,
 // during the previous target's integration
 enum { S_ITEM = 0, S_AVAIL, S_CLAIM, S_DONE, S_OVF, S_TOTAL, S_PRE, S_WALKED,
-       // a walk by two waves: the claim's generation, their meetings, the next
+       // a walk by several waves: the claim's generation, their meetings, the next
        // frontier's length (three by level), the accepted count, an overflow
        S_PGEN, S_PMEET, S_PNEXT, S_PACC = S_PNEXT + 3, S_POVF, S_COUNT = 16 };
 
@@ -1519,13 +1519,14 @@ __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx
     }
 }
 
-// The same walk by two waves (half 0 and 1) of one workgroup, into a list that
-// is read only once the walk is done: the batches of a level alternate
-// between the waves, their appends to the next frontier and to the accepted
+// The same walk by K waves (half 0 to K - 1) of one workgroup, into a list
+// that is read only once the walk is done: the batches of 64 nodes of a level
+// go round the waves, their appends to the next frontier and to the accepted
 // list are reserved by LDS atomics, and the waves meet at an LDS counter after
-// every level (both leave the loop at the same level).  sc[S_PMEET],
+// every level (all leave the loop at the same level).  sc[S_PMEET],
 // sc[S_PNEXT], sc[S_PACC], sc[S_POVF] and cur[0] = root are set by half 0
-// before either starts.  Half 0 publishes the list.
+// before any starts.  Half 0 publishes the list.
+template <int K>
 __device__ void walk_target_pair(const SweepArgs &a, int half, const int *per, int tx, int ty, int tz, int *fr0,
                                  int *fr1, int *acc, int *sc, int fmax, int amax, double &n_test, bool dev_lists)
 {
@@ -1536,7 +1537,7 @@ __device__ void walk_target_pair(const SweepArgs &a, int half, const int *per, i
         int *const next_count = &sc[S_PNEXT + lev % 3];
         // the counter of the level after next is free (read before the last meeting)
         if (half == 0 && lane == 0) sc[S_PNEXT + (lev + 1) % 3] = 0;
-        for (int base = 64 * half; base < nfr; base += 128) {
+        for (int base = 64 * half; base < nfr; base += 64 * K) {
             const int idx = base + lane;
             const bool valid = idx < nfr;
             int n = 0, nch = 0, fc = 0;
@@ -1585,17 +1586,17 @@ __device__ void walk_target_pair(const SweepArgs &a, int half, const int *per, i
             oa = __shfl(oa, 0, 64);
             on = __shfl(on, 0, 64);
             if (oa + cacc > amax || on + tot > fmax) {
-                // nothing is written; both waves stop after this level's meeting
+                // nothing is written; all waves stop after this level's meeting
                 if (lane == 0) sc[S_POVF] = lev + 1;
                 continue;
             }
             if (acc_it) acc[oa + __popcll(macc & ((1ull << lane) - 1ull))] = n;
             for (int c = 0; c < nch; ++c) nxt[on + off + c] = fc + c;
         }
-        // meet the other wave: the level's appends are all written
+        // meet the other waves: the level's appends are all written
         if (dev_lists) wait_stores();
         if (lane == 0) atomicAdd(&sc[S_PMEET], 1);
-        while (lds_load(&sc[S_PMEET]) < 2 * (lev + 1)) __builtin_amdgcn_s_sleep(1);
+        while (lds_load(&sc[S_PMEET]) < K * (lev + 1)) __builtin_amdgcn_s_sleep(1);
         nfr = uniform(lds_load(next_count));
         // (an overflow of the other wave's next level is not this level's)
         const int ov = uniform(lds_load(&sc[S_POVF]));
@@ -1699,7 +1700,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         sc[S_PGEN] = sc[S_COUNT + S_PGEN] = 0;   // (generations start at 1)
     }
     int bank = 0;
-    int titer = 0;   // targets begun by this workgroup (the generation of a paired walk's claim)
+    int titer = 0;   // targets begun by this workgroup (the generation of a shared walk's claim)
     int cached_dom = -1, cached_tsize = -1;   // whose radial tables the LDS holds
     for (;;) {
         int *const scb = sc + bank * S_COUNT;
@@ -1862,11 +1863,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             if (pass == 0) n_acc += (wave == 0 && lane == 0) ? (double)scb[S_TOTAL] : 0.0;
 
             // --- per-ray integration and the sum over rays (rays without emission give 0),
-            // by waves 0 .. IW - 1; the last wave meanwhile walks the next target ---
-            // (at 16 waves the last two walk the next target, else the last one: with
-            // fewer waves one more integrating wave is worth more than a faster walk)
-            constexpr bool kPair = WAVES >= 16;
-            constexpr int IW = kPair ? WAVES - 2 : (WAVES > 1 ? WAVES - 1 : 1);
+            // by waves 0 .. IW - 1; the others meanwhile walk the next target ---
+            // (at 16 waves the last four walk it, else the last one: with fewer waves
+            // one more integrating wave is worth more than a faster walk; at 16 the
+            // walk on fewer waves outlasts the integration, on more it slows it)
+            constexpr int kWalk = WAVES >= 16 ? 4 : 1;   // waves that walk the next target
+            constexpr bool kPair = kWalk > 1;
+            constexpr int IW = kPair ? WAVES - kWalk : (WAVES > 1 ? WAVES - 1 : 1);
             double fsum = 0.0;
             float cs_hi = 0.0f, cs_lo = 0.0f;   // compensated FP32 sum of this lane's FP32-marched rays
             if (wave >= IW) {
@@ -1971,9 +1974,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 }
             }
             // the next target: claimed and walked into the other bank by the last
-            // wave, or the last two (the node lists and that bank are not in use
+            // wave, or the last four (the node lists and that bank are not in use
             // until the next barrier)
-            if ((kPair ? wave >= WAVES - 2 : wave == WAVES - 1) && pass == npass - 1) {
+            if ((kPair ? wave >= WAVES - kWalk : wave == WAVES - 1) && pass == npass - 1) {
                 int *const nsc = sc + (bank ^ 1) * S_COUNT;
                 const int half = WAVES - 1 - wave;
                 if (half == 0) {
@@ -1982,7 +1985,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                         nsc[S_PRE] = 1;
                     }
                 } else {
-                    // the other wave's claim of this generation
+                    // half 0's claim of this generation
                     while (lds_load(&nsc[S_PGEN]) != titer) __builtin_amdgcn_s_sleep(1);
                 }
                 const int64_t nitem = uniform(lds_load(&nsc[S_ITEM]));
@@ -2021,7 +2024,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                         if (lane == 0) lds_store(&nsc[S_PGEN], titer);
                     }
                     if (walk)
-                        walk_target_pair(a, half, nper, ntx, nty, ntz, fr0, fr1, acc, nsc, fmax, amax, n_test, FALLBACK);
+                        walk_target_pair<kWalk>(a, half, nper, ntx, nty, ntz, fr0, fr1, acc, nsc, fmax, amax, n_test,
+                                                FALLBACK);
                 }
             }
             ftarget += fsum + ((double)cs_hi + (double)cs_lo);

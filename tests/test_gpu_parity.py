@@ -355,7 +355,7 @@ def test_few_targets_with_long_walks(T, orc):
     # second pass runs more workgroups than the first, each with its own
     # buffer slab
     rng = np.random.default_rng(26)
-    # (at 16 waves the next target is walked by two waves, here with device lists)
+    # (at 16 waves the next target is walked by four waves, here with device lists)
     cases = [(W.small_lognormal(16, n_src=2, seed=25), T.TR_FP64, 2, 0, 4),
              (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 2, 0, 4),
              (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 1, 1, 16),
