@@ -22,6 +22,7 @@ in the oracle are excluded and counted).
                     [--cpu-sample N] [--cpu-sample-1core N]
                     [--launch-fp32c W,T,B,I,A] [--launch-fp64 W,T,B,I,A] [--autotune]
                     [--n-src N] [--copy-mib M] [--theta T] [--theta-if T] [--theta-src T]
+                    [--per-domain K]
 
 --launch-* fix the sweep's launch shape (waves per target, targets per CU,
 buffer 1 = LDS / 2 = device memory, integration 1 = a lane per ray / 2 = a
@@ -31,7 +32,9 @@ compare-and-swap); without them the shape the autotuner found for the
 workload is used (configs 2 and 5), or searched (--autotune, other workloads);
 --n-src N replaces the workload by the config-3 grid with N equal sources
 (the source-count scaling); --copy-mib adds plain device copies of known
-size, the calibration of the HBM byte counters in a profiled run.
+size, the calibration of the HBM byte counters in a profiled run;
+--per-domain K times K sweeps of every domain of a multi-domain workload in a
+context of its own, one after another, against the one batched launch.
 """
 import argparse
 import json
@@ -87,6 +90,8 @@ def parse():
     ap.add_argument("--theta", type=float, default=None, help="override the opening angle")
     ap.add_argument("--theta-if", type=float, default=None, help="IF MAC opening angle")
     ap.add_argument("--theta-src", type=float, default=None, help="Src MAC opening angle")
+    ap.add_argument("--per-domain", type=int, default=0,
+                    help="also time this many sweeps of every domain in a context of its own (multi-domain workloads)")
     return ap.parse_args()
 
 
@@ -257,6 +262,42 @@ def main():
         k64 = args.steps if args.forms == "fp64" else max(1, min(args.fp64_steps, args.steps))
         forms["f64"] = run_form(T.TR_FP64, args.launch_fp64, k64, args.fp64_warmup, min(args.graph_steps, 1))
 
+    per_domain = None
+    if args.per_domain > 0 and len(P.domains) > 1:
+        # the same sweep of the main form with every domain in a context of its
+        # own, one after another, at the batched launch shape
+        rf = forms["f32"] if "f32" in forms else forms["f64"]
+        prec = T.TR_FP32C if "f32" in forms else T.TR_FP64
+        off = np.cumsum([0] + [d.n_cells() for d in P.domains])
+        kernel_ms = 0.0
+        wall = 0.0
+        for d in range(len(P.domains)):
+            Pd = W.Problem(f"{P.name}_domain{d}", [P.domains[d]], [P.n_h[d]], [P.src_xyz[d]], [P.src_q[d]],
+                           P.params)
+            lo, hi = int(off[d]), int(off[d + 1])
+            with T.context_for(Pd, prec) as c:
+                fp = f_thin[lo:hi].clone()
+                fo = torch.zeros_like(fp)
+                io = torch.zeros(hi - lo, dtype=torch.uint8, device="cuda")
+                c.build(nh[lo:hi].clone(), fp)
+                c.set_launch(*(int(x) for x in rf["launch"].split(",")))
+                c.sweep(fo, io)
+                c.sync()
+                ms = []
+                t0 = time.perf_counter()
+                for _ in range(args.per_domain):
+                    c.sweep(fo, io)
+                    c.sync()
+                    ms.append(c.stats().last_sweep_ms)
+                wall += (time.perf_counter() - t0) / args.per_domain
+                kernel_ms += float(np.mean(ms))
+        per_domain = {"contexts": len(P.domains), "launch": rf["launch"], "sweeps_each": args.per_domain,
+                      "sweep_ms_sum": round(kernel_ms, 3), "wall_ms_sum": round(wall * 1e3, 3),
+                      "batched_sweep_ms": round(rf["sweep_ms"], 3),
+                      "batched_over_sequential": round(rf["sweep_ms"] / kernel_ms, 4)}
+        log(f"per-domain contexts: {kernel_ms:.2f} ms of sweeps one after another against "
+            f"{rf['sweep_ms']:.2f} ms batched")
+
     if args.copy_mib > 0:
         # calibration for the HBM byte counters: plain copies of known size
         n = args.copy_mib * (1 << 20) // 4
@@ -343,6 +384,8 @@ def main():
         line["speedup_vs_fp64"] = round(r["value"] / r64["value"], 3)
         line["sweep_speedup_vs_fp64"] = round(r64["sweep_ms"] / r["sweep_ms"], 3)
 
+    if per_domain:
+        line["per_domain"] = per_domain
     if not args.no_cpu_baseline:
         line.update(cpu_baseline(args, P, forms, npix, W))
 
