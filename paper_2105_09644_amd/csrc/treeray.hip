@@ -1526,8 +1526,9 @@ __device__ void walk_target(const SweepArgs &a, int root, const int *per, int tx
 // every level (all leave the loop at the same level).  sc[S_PMEET],
 // sc[S_PNEXT], sc[S_PACC], sc[S_POVF] and cur[0] = root are set by half 0
 // before any starts.  Half 0 publishes the list.
+template <int K>
 __device__ void walk_target_pair(const SweepArgs &a, int half, const int *per, int tx, int ty, int tz, int *fr0,
-                                 int *fr1, int *acc, int *sc, int fmax, int amax, double &n_test, bool dev_lists, int K)
+                                 int *fr1, int *acc, int *sc, int fmax, int amax, double &n_test, bool dev_lists)
 {
     const int lane = lane_id();
     int *cur = fr0, *nxt = fr1;
@@ -1614,27 +1615,6 @@ __device__ void walk_target_pair(const SweepArgs &a, int half, const int *per, i
         lds_store(&sc[S_DONE], 1);
         sc[S_WALKED] = 1;
     }
-}
-
-// The ray batches of the class-sized integration: nb[q] batches of class q + 2
-// (64 >> (q + 2) rays of 4 << q lanes; class 7: a ray per wave), from the rays'
-// masks of emitting points; re = the rays in classes above the launch's group.
-__device__ inline int count_batches(const unsigned long long *emask, int ew, int np, int lg0, int lane, int nb[6], int &re)
-{
-    int n[6] = {0, 0, 0, 0, 0, 0};
-    for (int base = 0; base < np; base += 64) {
-        int tp;
-        const int c = ray_class(emask, ew, np, lg0, base + lane, tp);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) n[q] += (int)__popcll(__ballot(c == q + 2));
-    }
-    re = 0;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        nb[q] = q == 5 ? n[q] : (n[q] + (64 >> (q + 2)) - 1) >> (4 - q);
-        if (q + 2 > lg0) re += n[q];
-    }
-    return nb[0] + nb[1] + nb[2] + nb[3] + nb[4] + nb[5];
 }
 
 // The sweep of one launch.  FALLBACK: the second pass over the items whose
@@ -1886,27 +1866,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             // by waves 0 .. IW - 1; the others meanwhile walk the next target ---
             // (at 16 waves the last four walk it, else the last one: with fewer waves
             // one more integrating wave is worth more than a faster walk; at 16 the
-            // walk on fewer waves outlasts the integration, on more it slows it.  At
-            // 8 waves a target whose integration is light (class-sized groups with
-            // the FP32 march, at most one ray batch per integrating wave; the FP64
-            // march's batches outlast the walk) is walked by the last two:
-            // every wave counts the batches from the same masks, final at the
-            // mapping's barrier, so all take the same decision)
+            // walk on fewer waves outlasts the integration, on more it slows it)
             constexpr int kWalk = WAVES >= 16 ? 4 : 1;   // waves that walk the next target
-            const int lg0 = a.int_group > 0 ? 31 - __clz(a.int_group) : 0;
-            int nb[6] = {0, 0, 0, 0, 0, 0};
-            int n_batch = 0, n_walk = kWalk;
-            bool counted = false;
-            if constexpr (WAVES == 8) {
-                if (a.int_group > 0 && a.int_fp32) {
-                    counted = true;
-                    int re;
-                    n_batch = count_batches(emask, ew, np, lg0, lane, nb, re);
-                    n_re += (wave == 0 && lane == 0) ? (double)re : 0.0;
-                    if (n_batch <= WAVES - 2) n_walk = 2;
-                }
-            }
-            const int IW = n_walk > 1 ? WAVES - n_walk : (WAVES > 1 ? WAVES - 1 : 1);
+            constexpr bool kPair = kWalk > 1;
+            constexpr int IW = kPair ? WAVES - kWalk : (WAVES > 1 ? WAVES - 1 : 1);
             double fsum = 0.0;
             float cs_hi = 0.0f, cs_lo = 0.0f;   // compensated FP32 sum of this lane's FP32-marched rays
             if (wave >= IW) {
@@ -1918,11 +1881,25 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 // class share a batch of 64 / g rays of g lanes; the batches, widest
                 // class first and pixel order within a class, are dealt round robin
                 // over the waves.
-                if (!counted) {
-                    int re;
-                    n_batch = count_batches(emask, ew, np, lg0, lane, nb, re);
+                const int lg0 = 31 - __clz(a.int_group);
+                int nb[6];   // batches of classes 2 .. 7 (class 7: a ray each)
+                {
+                    int n[6] = {0, 0, 0, 0, 0, 0};
+                    for (int base = 0; base < np; base += 64) {
+                        int tp;
+                        const int c = ray_class(emask, ew, np, lg0, base + lane, tp);
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) n[q] += (int)__popcll(__ballot(c == q + 2));
+                    }
+                    int re = 0;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        nb[q] = q == 5 ? n[q] : (n[q] + (64 >> (q + 2)) - 1) >> (4 - q);
+                        if (q + 2 > lg0) re += n[q];
+                    }
                     n_re += (wave == 0 && lane == 0) ? (double)re : 0.0;
                 }
+                const int n_batch = nb[0] + nb[1] + nb[2] + nb[3] + nb[4] + nb[5];
                 for (int b = wave; b < n_batch; b += IW) {
                     int cls = -1, bi = b;
 #pragma unroll
@@ -1999,7 +1976,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             // the next target: claimed and walked into the other bank by the last
             // wave, or the last four (the node lists and that bank are not in use
             // until the next barrier)
-            if (wave >= WAVES - n_walk && pass == npass - 1) {
+            if ((kPair ? wave >= WAVES - kWalk : wave == WAVES - 1) && pass == npass - 1) {
                 int *const nsc = sc + (bank ^ 1) * S_COUNT;
                 const int half = WAVES - 1 - wave;
                 if (half == 0) {
@@ -2028,7 +2005,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                     }
                 }
                 const int *nper = a.periodic ? a.doms[ndom].ext : nullptr;
-                if (n_walk == 1) {
+                if (!kPair) {
                     if (walk) {
                         walk_target(a, a.doms[ndom].root, nper, ntx, nty, ntz, fr0, fr1, acc, nsc, fmax, amax, n_test,
                                     FALLBACK);
@@ -2047,8 +2024,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                         if (lane == 0) lds_store(&nsc[S_PGEN], titer);
                     }
                     if (walk)
-                        walk_target_pair(a, half, nper, ntx, nty, ntz, fr0, fr1, acc, nsc, fmax, amax, n_test, FALLBACK,
-                                         n_walk);
+                        walk_target_pair<kWalk>(a, half, nper, ntx, nty, ntz, fr0, fr1, acc, nsc, fmax, amax, n_test,
+                                                FALLBACK);
                 }
             }
             ftarget += fsum + ((double)cs_hi + (double)cs_lo);

@@ -355,25 +355,21 @@ def test_few_targets_with_long_walks(T, orc):
     # second pass runs more workgroups than the first, each with its own
     # buffer slab
     rng = np.random.default_rng(26)
-    # (at 16 waves the next target is walked by four waves, at 8 waves with
-    # class-sized groups (integration 3 or 6) and few emitting rays by two, here
-    # with device lists)
-    cases = [(W.small_lognormal(16, n_src=2, seed=25), T.TR_FP64, 2, 0, 4, 0),
-             (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 2, 0, 4, 0),
-             (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 1, 1, 16, 0),
-             (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 1, 1, 8, 6),
-             (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP64, 2, 0, 8, 3),
-             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP32C, 1, 2, 4, 0),
-             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP64, 1, 3, 4, 0),
-             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP64, 1, 3, 16, 0)]
-    for P, prec, buf, where, waves, intm in cases:
+    # (at 16 waves the next target is walked by four waves, here with device lists)
+    cases = [(W.small_lognormal(16, n_src=2, seed=25), T.TR_FP64, 2, 0, 4),
+             (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 2, 0, 4),
+             (W.small_lognormal(16, n_src=2, seed=25), T.TR_FP32C, 1, 1, 16),
+             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP32C, 1, 2, 4),
+             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP64, 1, 3, 4),
+             (W.small_lognormal(16, n_src=2, seed=27, nside=4, n_radial=64), T.TR_FP64, 1, 3, 16)]
+    for P, prec, buf, where, waves in cases:
         tg = np.sort(rng.choice(P.total_cells(), 37, replace=False))
         f0, i0 = orc_sweep(orc, P, thin=True, targets=tg, theta=0.05)
-        g0, j0, st = gpu_sweep(T, P, prec, thin=True, targets=tg, launch=(waves, 0, buf, intm, 0), theta=0.05)
+        g0, j0, st = gpu_sweep(T, P, prec, thin=True, targets=tg, launch=(waves, 0, buf, 0, 0), theta=0.05)
         assert st.overflow == 0 and st.buffer_in_lds == where
         assert st.nodes_accepted / len(tg) > 2048
         compare(g0, j0, f0, i0, TOL64 if prec == T.TR_FP64 else TOL32,
-                name=f"37 targets prec {prec} buffer {buf} waves {waves} integration {intm}")
+                name=f"37 targets prec {prec} buffer {buf} waves {waves}")
 
 
 @pytest.mark.parametrize("radius_cells", [0.45, 1.7])
